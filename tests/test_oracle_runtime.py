@@ -1,0 +1,234 @@
+"""Pins of the oracle's runtime path: table interpolation, inverse-CDF
+sampling, the optical-depth step, kinematics and the ordered append.
+
+Statistical pins compare Monte Carlo outcomes with the integrated cross
+sections (event fractions) and with quadrature CDFs (spectra)."""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import qed_inputs as QI
+from oracle import oracle as O
+
+R0 = O.rate_prefactor()
+
+
+@pytest.fixture(scope="module")
+def tables64():
+    return (O.Table(O.BW, 1e-3, 1e2, 64, 64), O.Table(O.QS, 1e-3, 1e2, 64, 64))
+
+
+def test_rate_exact_at_knots_and_linear_in_log_between(tables64):
+    bw, qs = tables64
+    chi = bw.chi_grid()
+    for n in (0, 1, 17, 62, 63):
+        g = 7.0
+        assert bw.rate(chi[n], g) == pytest.approx(R0 * chi[n] / g * math.exp(bw.ln_rate[n]), rel=1e-13)
+        assert qs.rate(chi[n], g) == pytest.approx(2 / 3 * R0 * math.exp(qs.ln_rate[n]) / g, rel=1e-13)
+    # between knots: the paper's formula ln T* = ln T_n + (ln chi* - ln chi_n) slope
+    rng = np.random.default_rng(3)
+    lc = np.log(chi)
+    for x in rng.uniform(lc[0], lc[-1], 200):
+        ref_lnT = np.interp(x, lc, bw.ln_rate)
+        ref_lnG = np.interp(x, lc, qs.ln_rate)
+        c = math.exp(x)
+        assert bw.rate(c, 3.0) == pytest.approx(R0 * c / 3.0 * math.exp(ref_lnT), rel=1e-12)
+        assert qs.rate(c, 3.0) == pytest.approx(2 / 3 * R0 * math.exp(ref_lnG) / 3.0, rel=1e-12)
+
+
+def test_rate_out_of_table_rules(tables64):
+    bw, qs = tables64
+    # QS: first / last stored value (Sec. 3.2), including chi = 0
+    assert qs.rate(0.0, 2.0) == pytest.approx(2 / 3 * R0 * math.exp(qs.ln_rate[0]) / 2.0, rel=1e-15)
+    assert qs.rate(1e6, 2.0) == pytest.approx(2 / 3 * R0 * math.exp(qs.ln_rate[-1]) / 2.0, rel=1e-15)
+    # BW: asymptotic forms matched at the edges; continuous there; zero at chi = 0
+    assert bw.rate(0.0, 10.0) == 0.0
+    for edge in (bw.chi_min, bw.chi_max):
+        lo, hi = bw.rate(edge * (1 - 1e-12), 10.0), bw.rate(edge * (1 + 1e-12), 10.0)
+        assert lo == pytest.approx(hi, rel=1e-9)
+    assert bw.rate(1e-4, 10.0) < 1e-300 * R0
+
+
+def test_sampling_inverts_table_at_knots(tables64):
+    bw, qs = tables64
+    chi = bw.chi_grid()
+    xi_bw, xi_qs = bw.frac_grid(), qs.frac_grid()
+    for n in (5, 40, 63):
+        for m in range(1, 63, 7):
+            p = bw.cdf[n, m]
+            if 0 < p < 0.5:
+                xi, esel = bw.sample_bw(chi[n], p)
+                assert esel and xi == pytest.approx(xi_bw[m], rel=1e-9, abs=1e-12)
+                if p > 1e-3:   # 1 - (1 - p) reproduces p only to ~1e-16 absolute
+                    xi2, esel2 = bw.sample_bw(chi[n], 1 - p)
+                    assert not esel2 and xi2 == pytest.approx(xi_bw[m], rel=1e-9, abs=1e-12)
+            lnxi = qs.sample_qs_lnxi(chi[n], math.exp(qs.cdf[n, m]))
+            assert lnxi == pytest.approx(math.log(xi_qs[m]), rel=1e-9, abs=1e-9)
+
+
+def test_qs_sampler_below_first_knot_is_cube_law(tables64):
+    _, qs = tables64
+    chi = 0.5
+    L0 = np.interp(np.log(chi), np.log(qs.chi_grid()), qs.cdf[:, 0])
+    for k in (1.0, 5.0):
+        r = math.exp(L0 - k)
+        assert qs.sample_qs_lnxi(chi, r) == pytest.approx(math.log(1e-12) - 3 * k, rel=1e-13)
+
+
+def _ks(samples, cdf_fn, grid):
+    """sup over grid of |ECDF - CDF|."""
+    s = np.sort(samples)
+    e = np.searchsorted(s, grid, side="right") / len(s)
+    return np.max(np.abs(e - np.array([cdf_fn(x) for x in grid])))
+
+
+@pytest.mark.parametrize("chi", [0.05, 1.0, 20.0])
+def test_qs_photon_spectrum_matches_cross_section(chi):
+    """Photon chi fractions sampled through a fine table follow the QS
+    cumulative distribution computed by quadrature (KS)."""
+    t = O.Table(O.QS, chi / 1.5, chi * 1.5, 3, 256)
+    rng = np.random.default_rng(11)
+    r = rng.random(1 << 20)
+    xi = np.exp(t.sample_n(chi, r))
+    qs_grid = np.quantile(xi, np.linspace(0.02, 0.98, 25))
+    ks = _ks(xi, lambda x: O.qs_cdf_at(chi, x), qs_grid)
+    assert ks < 3e-3, ks
+
+
+@pytest.mark.parametrize("chi", [0.05, 1.0, 20.0])
+def test_bw_pair_spectrum_matches_cross_section(chi):
+    t = O.Table(O.BW, chi / 1.5, chi * 1.5, 3, 256)
+    rng = np.random.default_rng(12)
+    r = rng.random(1 << 20)
+    xi, esel = t.sample_n(chi, r)
+    # electron fraction; symmetric under xi -> 1 - xi
+    xe = np.where(esel, xi, 1 - xi)
+    assert abs(esel.mean() - 0.5) < 5 * 0.5 / math.sqrt(len(r))
+    folded = np.minimum(xe, 1 - xe)
+    grid = np.quantile(folded, np.linspace(0.02, 0.98, 25))
+    ks = _ks(folded, lambda x: 2 * O.bw_cdf_at(chi, x), grid)
+    assert ks < 3e-3, ks
+
+
+def _fixed_population(n, gamma, e_field, photon):
+    u = gamma if photon else math.sqrt(gamma * gamma - 1)
+    z = np.zeros(n)
+    return dict(ux=np.full(n, -u), uy=z.copy(), uz=z.copy(), ex=z.copy(), ey=np.full(n, e_field),
+                ez=z.copy(), bx=z.copy(), by=z.copy(), bz=np.full(n, e_field / QI.C_LIGHT),
+                w=np.linspace(0.5, 1.5, n))
+
+
+@pytest.mark.parametrize("photon", [False, True])
+def test_event_fraction_matches_total_rate(tables64, photon):
+    """With tau ~ Exp(1), the fraction of particles with an event in each step
+    is 1 - exp(-rate dt) (memoryless), rate = dN/dt from the tables."""
+    bw, qs = tables64
+    n, gamma, e = 1 << 18, 2000.0, 2e14
+    pop = _fixed_population(n, gamma, e, photon)
+    sp = O.PHOTON if photon else O.ELECTRON
+    p = O.Particles(pop, sp, id_base=1000)
+    O.init_optical_depth(p, seed=5)
+    chi = O.chi_photon(*[pop[k][0] for k in ("ux", "uy", "uz", "ex", "ey", "ez", "bx", "by", "bz")]) \
+        if photon else O.chi_lepton(*[pop[k][0] for k in ("ux", "uy", "uz", "ex", "ey", "ez", "bx", "by", "bz")])
+    rate = (bw if photon else qs).rate(chi, gamma)
+    dt = 0.2 / rate
+    prob = 1 - math.exp(-rate * dt)
+    a1, a2 = O.Append(n), O.Append(n)
+    tot = 0
+    steps = 1 if photon else 3   # a photon decays once and is dead afterwards
+    for s in range(steps):
+        tot += O.step(bw, qs, p, dt, seed=5, step_idx=s, a1=a1, a2=a2)
+    mean = steps * n * prob
+    sd = math.sqrt(steps * n * prob * (1 - prob))
+    assert abs(tot - mean) < 5 * sd
+    assert a1.count == tot
+
+
+def test_step_kinematics_conservation_and_order(tables64):
+    bw, qs = tables64
+    el, ph = QI.c1_population(seed=1, n=1 << 12)
+    for pop, sp in ((el, O.ELECTRON), (ph, O.PHOTON)):
+        p = O.Particles(pop, sp, id_base=77)
+        O.init_optical_depth(p, seed=1)
+        u0 = np.stack([p["ux"].copy(), p["uy"].copy(), p["uz"].copy()], 1)
+        tau0 = p["tau"].copy()
+        a1, a2 = O.Append(1 << 12), O.Append(1 << 12)
+        flags = np.zeros(p.n, dtype=np.uint8)
+        ev = O.step(bw, qs, p, 1e-16, seed=1, step_idx=3, a1=a1, a2=a2, flags=flags)
+        idx = np.nonzero(flags)[0]
+        assert ev == len(idx) > 0
+        np.testing.assert_array_equal(a1["parent"], idx + 77)
+        assert np.all(np.diff(a1["parent"]) > 0)
+        np.testing.assert_array_equal(a1["w"], pop["w"][idx])
+        # non-event particles: tau decreased, momentum untouched
+        ne = flags == 0
+        assert np.all(p["tau"][ne] <= tau0[ne])
+        u1 = np.stack([p["ux"], p["uy"], p["uz"]], 1)
+        np.testing.assert_array_equal(u1[ne], u0[ne])
+        umag = np.linalg.norm(u0[idx], axis=1, keepdims=True)
+        if sp == O.ELECTRON:
+            pg = np.stack([a1["ux"], a1["uy"], a1["uz"]], 1)
+            np.testing.assert_allclose(u1[idx] + pg, u0[idx], rtol=0, atol=1e-15 * float(umag.max()) * 4)
+            # redrawn parent tau is -ln(u1) of the event block
+            for j in idx[:50]:
+                d = O.draws(1, 77 + j, 3, O.ELECTRON)
+                assert p["tau"][j] == -math.log(d[1])
+                assert a1["tau"][list(idx).index(j)] == -math.log(d[2])
+        else:
+            pe = np.stack([a1["ux"], a1["uy"], a1["uz"]], 1)
+            pp = np.stack([a2["ux"], a2["uy"], a2["uz"]], 1)
+            np.testing.assert_allclose(pe + pp, u0[idx], rtol=0, atol=1e-15 * float(umag.max()) * 4)
+            assert np.all(np.isinf(p["tau"][idx]))
+            np.testing.assert_array_equal(a2["parent"], a1["parent"])
+            # collinear products: both along the photon
+            cos = np.sum(pe * u0[idx], 1) / (np.linalg.norm(pe, axis=1) * umag[:, 0])
+            np.testing.assert_allclose(cos, 1.0, atol=1e-12)
+            # energy defect of collinear massive products <= (1/(2 g))(1/xi + 1/(1 - xi))
+            ge = np.sqrt(1 + np.sum(pe * pe, 1))
+            gp = np.sqrt(1 + np.sum(pp * pp, 1))
+            gg = umag[:, 0]
+            xi = np.linalg.norm(pe, axis=1) / gg
+            bound = (1 / (2 * gg)) * (1 / xi + 1 / (1 - xi))
+            assert np.all(ge + gp - gg <= bound * (1 + 1e-9) + 1e-12)
+
+
+def test_init_optical_depth_keying():
+    pop = _fixed_population(64, 10.0, 1e12, False)
+    p = O.Particles(pop, O.POSITRON, id_base=2**40)
+    O.init_optical_depth(p, seed=9)
+    for i in (0, 13, 63):
+        ctr = [2**40 + i, 2**64 - 1, O.POSITRON, 0]
+        v = sum(c << (64 * k) for k, c in enumerate(ctr)) - 1
+        g = np.random.Philox(key=np.array([9, 0], dtype=np.uint64),
+                             counter=np.array([(v >> (64 * k)) & (2**64 - 1) for k in range(4)], dtype=np.uint64))
+        w = int(g.random_raw(1)[0])
+        assert p["tau"][i] == -math.log((2 * (w >> 12) + 1) / 2.0**53)
+
+
+def test_capacity_and_threshold(tables64):
+    bw, qs = tables64
+    el, _ = QI.c1_population(seed=2, n=1 << 12)
+    ref = O.Particles(el, O.ELECTRON)
+    O.init_optical_depth(ref, seed=2)
+    small = O.Particles(el, O.ELECTRON, tau=ref["tau"])
+    a_full, a_small = O.Append(1 << 12), O.Append(10)
+    n_full = O.step(bw, qs, ref, 1e-16, 2, 0, a_full)
+    O.step(bw, qs, small, 1e-16, 2, 0, a_small)
+    assert a_small.count == a_full.count == n_full > 10
+    np.testing.assert_array_equal(a_small["ux"], a_full["ux"][:10])
+    np.testing.assert_array_equal(small["ux"], ref["ux"])
+    # threshold: photons below it are dropped but the parent still recoils
+    thr = O.Particles(el, O.ELECTRON, tau=small["tau"] * 0 + ref["tau"])
+    base = O.Particles(el, O.ELECTRON, tau=ref["tau"])
+    O.init_optical_depth(base, 2)
+    O.init_optical_depth(thr, 2)
+    a_b, a_t = O.Append(1 << 12), O.Append(1 << 12)
+    O.step(bw, qs, base, 1e-16, 2, 0, a_b)
+    O.step(bw, qs, thr, 1e-16, 2, 0, a_t, photon_min_energy=2.0)
+    gg = np.linalg.norm(np.stack([a_b["ux"], a_b["uy"], a_b["uz"]], 1), axis=1)
+    keep = gg >= 2.0
+    assert a_t.count == int(keep.sum()) < a_b.count
+    np.testing.assert_array_equal(a_t["parent"], a_b["parent"][keep])
+    np.testing.assert_array_equal(thr["ux"], base["ux"])
