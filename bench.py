@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Throughput of the fused QED step on one MI355X.
+
+Workload (default): 2^24 leptons + 2^24 photons, momenta in a 0.1 rad cone
+about -x with gamma log-uniform in [1e2, 1e5], linearly polarised plane-wave
+fields with a0 log-uniform in [10, 1000], 256 x 256 tables over chi in
+[1e-4, 1e3], dt = 0.1 fs.  One "step" is one qed_step over all 2^25
+particles (chi, rate, tau update, events, sampling, product append).
+
+value = FP64 table-path particle updates per second over the timed steps;
+the FP32 path is reported beside it.  Inputs are resident in HBM before the
+timed region; product buffers are emptied (one 3-element fill) before each
+step, as a PIC code does when it merges the products.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "QED particle updates/s at 1 MI355X (FP64 table vs FP32+surrogate), % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic bytes: per update, and extra per event
+BYTES = {
+    "f64": dict(base=88, qs_event=80, bw_event=104),
+    "f32": dict(base=44, qs_event=44, bw_event=60),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_tables(Q, n_chi, n_frac, chi_range):
+    bw = Q.Table.generate(Q.BW, chi_range[0], chi_range[1], n_chi, n_frac).to_device()
+    qs = Q.Table.generate(Q.QS, chi_range[0], chi_range[1], n_chi, n_frac, 1e-12).to_device()
+    return bw, qs
+
+
+def run_path(Q, torch, ctx, tables, pops, dtype, steps, warmup, dt, chi_mode, seed=1):
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    el, ph = pops
+    dev = []
+    for pop in (el, ph):
+        d = {k: torch.as_tensor(v).to("cuda", dtype=tdt) for k, v in pop.items()}
+        d["tau"] = torch.empty_like(d["ux"])
+        dev.append(d)
+    n_e, n_g = len(el["ux"]), len(ph["ux"])
+    pe = Q.particles(dev[0], Q.ELECTRON, 0)
+    pg = Q.particles(dev[1], Q.PHOTON, n_e)
+    Q.init_optical_depth(ctx, pe, seed)
+    Q.init_optical_depth(ctx, pg, seed)
+    counts = torch.zeros(3, dtype=torch.int64, device="cuda")
+    cap = (n_e + n_g) // 2
+    bufs = []
+    for i in range(3):
+        b = Q.AppendBuffer(cap, tdt)
+        b.c.count = counts.data_ptr() + 8 * i
+        b.count = counts[i:i + 1]
+        bufs.append(b)
+    stats = torch.zeros(Q.STATS_LEN, dtype=torch.int64, device="cuda")
+    bw, qs = tables
+    desc = Q.StepDesc([pe, pg], bw=bw, qs=qs, photons=bufs[0], electrons=bufs[1], positrons=bufs[2],
+                      stats=stats, dt=dt, seed=seed, chi_mode=chi_mode)
+    step = 0
+    for _ in range(warmup):
+        counts.zero_()
+        desc.set_step(step)
+        Q.step(ctx, desc)
+        step += 1
+    torch.cuda.synchronize()
+    need = int(counts.max().item())
+    if need > cap:
+        raise RuntimeError(f"product capacity {cap} too small ({need})")
+    stats.zero_()
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        counts.zero_()
+        desc.set_step(step)
+        ev0[i].record()
+        Q.step(ctx, desc)
+        ev1[i].record()
+        step += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = np.array([a.elapsed_time(b) for a, b in zip(ev0, ev1)])
+    st = stats.cpu().numpy()
+    assert st[Q.STAT_SCAN_TIMEOUT] == 0, "look-back wait abandoned"
+    updates = int(st[Q.STAT_UPDATES])
+    assert updates == steps * (n_e + n_g)
+    qs_ev, bw_ev = int(st[Q.STAT_QS_EVENTS]), int(st[Q.STAT_BW_EVENTS])
+    by = BYTES[dtype]
+    alg_bytes = by["base"] * updates + by["qs_event"] * qs_ev + by["bw_event"] * bw_ev
+    kern_s = kern_ms.sum() / 1e3
+    res = dict(
+        updates_per_s=updates / wall,
+        ms_per_step=wall / steps * 1e3,
+        kernel_ms_mean=float(kern_ms.mean()),
+        kernel_ms_median=float(np.median(kern_ms)),
+        achieved_gbs=alg_bytes / kern_s / 1e9,
+        alg_bytes_per_launch=alg_bytes / steps,
+        qs_event_fraction=qs_ev / (steps * n_e),
+        bw_event_fraction=bw_ev / (steps * n_g),
+    )
+    del dev, bufs
+    return res
+
+
+def cpu_baseline(pops_small, tables_params, dt, seed=1):
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    from oracle import oracle as O
+    n_chi, n_frac, rng = tables_params
+    log("cpu_baseline: generating oracle tables")
+    obw = O.Table(O.BW, rng[0], rng[1], n_chi, n_frac)
+    oqs = O.Table(O.QS, rng[0], rng[1], n_chi, n_frac)
+    el, ph = pops_small
+    oe, og = O.Particles(el, O.ELECTRON, 0), O.Particles(ph, O.PHOTON, 1 << 40)
+    O.init_optical_depth(oe, seed)
+    O.init_optical_depth(og, seed)
+    n = oe.n + og.n
+    a1, a2, a3 = O.Append(n), O.Append(n), O.Append(n)
+    steps = 2
+    log(f"cpu_baseline: timing {steps} oracle steps over {n} particles")
+    t0 = time.perf_counter()
+    for s in range(steps):
+        a1.count = a2.count = a3.count = 0
+        O.step(obw, oqs, oe, dt, seed, s, a1)
+        O.step(obw, oqs, og, dt, seed, s, a2, a3)
+    wall = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=steps * n / wall, unit="particle updates/s", cores=cores, kind="oracle",
+                sample=f"{oe.n} leptons + {og.n} photons of the same workload, {steps} steps "
+                       f"(FP64 C oracle, OpenMP over particles, sequential append), {wall:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2n", type=int, default=24, help="particles per species = 2^log2n")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-log2n", type=int, default=17)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2110_00256_amd as Q
+    import qed_inputs as QI
+
+    n = 1 << args.log2n
+    dt = 1e-16
+    chi_range = (1e-4, 1e3)
+    log(f"bench: generating inputs 2^{args.log2n} leptons + 2^{args.log2n} photons")
+    pops = QI.c2_population(seed=1, n=n)
+    ctx = Q.Context(0)
+    log("bench: generating 256x256 tables")
+    tables = make_tables(Q, 256, 256, chi_range)
+    log("bench: FP64 table path")
+    r64 = run_path(Q, torch, ctx, tables, pops, "f64", args.steps, args.warmup, dt, Q.CHI_FP64)
+    log(f"bench: FP64 {r64['updates_per_s']:.3e} upd/s, kernel {r64['kernel_ms_mean']:.3f} ms")
+    r32 = None
+    if not args.no_fp32:
+        log("bench: FP32 table path")
+        r32 = run_path(Q, torch, ctx, tables, pops, "f32", args.steps, args.warmup, dt, Q.CHI_FP64)
+        log(f"bench: FP32 {r32['updates_per_s']:.3e} upd/s, kernel {r32['kernel_ms_mean']:.3f} ms")
+    cpu = None
+    if not args.no_cpu_baseline:
+        m = 1 << args.cpu_sample_log2n
+        small = tuple({k: v[:m] for k, v in p.items()} for p in pops)
+        cpu = cpu_baseline(small, (256, 256, chi_range), dt)
+        log(f"bench: oracle {cpu['value']:.3e} upd/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": r64["updates_per_s"],
+        "unit": "particle updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "cone plane wave: 2^24 leptons + 2^24 photons, 256x256 tables over chi "
+                               "[1e-4, 1e3], dt 0.1 fs, FP64 table path",
+                   "particles": 2 * n, "dt_s": dt, "table": "256x256",
+                   "qs_event_fraction": r64["qs_event_fraction"], "bw_event_fraction": r64["bw_event_fraction"]},
+        "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": r64["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "step_kernel<double>", "kernel_ms_mean": r64["kernel_ms_mean"],
+                     "alg_bytes_per_launch": r64["alg_bytes_per_launch"]},
+        "cpu_baseline": cpu,
+    }
+    if r32 is not None:
+        out["fp32_table_path"] = {
+            "value": r32["updates_per_s"], "ms_per_step": r32["ms_per_step"],
+            "kernel_ms_mean": r32["kernel_ms_mean"], "achieved_gbs": r32["achieved_gbs"],
+            "frac": r32["achieved_gbs"] / HBM_PEAK_GBS, "alg_bytes_per_launch": r32["alg_bytes_per_launch"],
+            "qs_event_fraction": r32["qs_event_fraction"], "bw_event_fraction": r32["bw_event_fraction"],
+            "speedup_vs_fp64": r32["updates_per_s"] / r64["updates_per_s"]}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

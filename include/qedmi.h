@@ -1,0 +1,302 @@
+/*
+ * qedmi.h -- C ABI of the MI355X strong-field QED Monte Carlo library.
+ *
+ * The library implements the per-timestep QED sub-step that a particle-in-
+ * cell code adds to its loop (Fedeli et al., "PICSAR-QED", arXiv:2110.00256,
+ * Fig. 1 and Sec. 3): the quantum parameter chi of each macro-particle, the
+ * optical-depth evolution with the tabulated total rates of nonlinear
+ * Breit-Wheeler pair production (BW) and quantum-synchrotron photon emission
+ * (QS), and, on an event, inverse-CDF sampling of the product, creation of
+ * the photon or pair, parent recoil and optical-depth redraw.
+ *
+ * Conventions shared by every call:
+ *   Units      momentum u = p/(m_e c) (dimensionless); E in V/m; B in T;
+ *              dt in s.  Photons carry u with gamma_gamma = |u|.
+ *   Memory     particle arrays and product buffers are caller-owned DEVICE
+ *              memory (SoA, one array per component, element type given by
+ *              `dtype`).  Tables, contexts and surrogates are library-owned
+ *              opaque handles.  Host pointers are marked "host".
+ *   Streams    `stream` is a hipStream_t passed as void* (NULL = default
+ *              stream).  Every device call is asynchronous on that stream;
+ *              only the calls documented as synchronous block the host.
+ *   Contexts   a qed_context owns per-device scratch (look-back status words,
+ *              chunk tickets, chunk tables).  Calls that share a context must
+ *              be ordered on one stream; concurrent calls on one context race.
+ *   Errors     every call returns int32_t: QED_OK (0) or a negative
+ *              qed_status; qed_last_error() gives a thread-local message.
+ *              Nothing aborts and no exception crosses the ABI.  Argument
+ *              checks happen on the host before any launch; a call that
+ *              returns an error has launched nothing.
+ *   Randomness every uniform comes from Philox4x64-10 (Salmon et al., SC'11)
+ *              with key (seed, 0) and counter (particle id, step, species,
+ *              block); the id of element i is id_base + i.  Results are
+ *              therefore independent of launch shape and bit-reproducible.
+ *              The paper leaves the generator to the caller (Sec. 3.3); this
+ *              library fixes a counter-based one so that results can be
+ *              reproduced exactly on the CPU.
+ */
+#ifndef QEDMI_H
+#define QEDMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QED_OK = 0,
+    QED_ERR_INVALID = -1,   /* bad argument (null pointer, size, enum, range) */
+    QED_ERR_HIP = -2,       /* a HIP runtime call failed                      */
+    QED_ERR_ALLOC = -3,     /* host or device allocation failed               */
+    QED_ERR_CAPACITY = -4,  /* product buffer too small (see qed_read_count)  */
+    QED_ERR_IO = -5,        /* file missing, short or corrupt                 */
+    QED_ERR_STATE = -6      /* object not ready (e.g. table not on device)    */
+} qed_status;
+
+typedef enum { QED_FP64 = 0, QED_FP32 = 1, QED_BF16 = 2 } qed_dtype;
+typedef enum { QED_PROC_BW = 0, QED_PROC_QS = 1 } qed_process;
+typedef enum { QED_ELECTRON = 0, QED_POSITRON = 1, QED_PHOTON = 2, QED_ION = 3 } qed_species;
+
+/* How chi is evaluated on FP32 particle data (FP64 data always uses FP64).
+ * QED_CHI_FP64: FP64 arithmetic on the FP32 inputs (default).
+ * QED_CHI_COMP32: FP32 pair ("double-float") arithmetic with error-free
+ *   transformations (TwoSum, TwoProd via fma) throughout.
+ * QED_CHI_FP32: plain FP32 (for precision studies only). */
+typedef enum { QED_CHI_FP64 = 0, QED_CHI_COMP32 = 1, QED_CHI_FP32 = 2 } qed_chi_mode;
+
+/* ------------------------------------------------------------------ tables
+ * Lookup tables of Sec. 3.1 (BW) and Sec. 3.2 (QS).  Grid: n_chi points
+ * ln chi_n = ln chi_min + n (ln chi_max - ln chi_min)/(n_chi - 1).
+ *   BW: ln_rate[n] = ln T(chi_n); cdf[n][m] = P(chi_n, xi_m), xi_m =
+ *       0.5 m/(n_frac - 1) (only xi <= 1/2 is stored, by the symmetry
+ *       P(xi) = 1 - P(1 - xi)).
+ *   QS: ln_rate[n] = ln G(chi_n); cdf[n][m] = ln P(chi_n, xi_m), ln xi_m =
+ *       ln frac_min (1 - m/(n_frac - 1)).
+ * cdf is row-major [n_chi][n_frac]. */
+typedef struct {
+    int32_t process;     /* qed_process                                   */
+    int32_t n_chi;       /* >= 2, <= 4096                                 */
+    int32_t n_frac;      /* >= 3, <= 4096                                 */
+    int32_t n_threads;   /* host threads for generation; <= 0: all cores  */
+    double chi_min;      /* > 0                                           */
+    double chi_max;      /* > chi_min                                     */
+    double frac_min;     /* QS xi_min in (0, 1); ignored for BW           */
+} qed_table_params;
+
+typedef struct qed_table qed_table;
+
+/* Generate both tables of one process from the Bessel-function integrals of
+ * Sec. 2.1 (T(chi_gamma), BW differential rate) or Sec. 2.2 (G(chi), S(chi,
+ * xi)), in FP64 on the host (the paper's generation is CPU-side, Sec. 3).
+ * Synchronous.  *out receives a new handle (caller destroys it). */
+int32_t qed_table_generate(const qed_table_params* params, qed_table** out);
+
+/* Wrap caller-provided FP64 host arrays (copied) as a table (e.g. tables
+ * produced elsewhere, Sec. 5: "load a lookup table generated beforehand"). */
+int32_t qed_table_from_host(const qed_table_params* params, const double* ln_rate,
+                            const double* cdf, qed_table** out);
+
+/* Save / load: little-endian header, parameters, FP64 payload, FNV-1a
+ * checksum.  load returns QED_ERR_IO on a missing, short or corrupt file. */
+int32_t qed_table_save(const qed_table* t, const char* path);
+int32_t qed_table_load(const char* path, qed_table** out);
+
+/* Borrow the FP64 host arrays (valid until destroy) and the parameters. */
+int32_t qed_table_host_data(const qed_table* t, const double** ln_rate, const double** cdf,
+                            qed_table_params* params);
+
+/* Copy the table to the current device in FP64, FP32 and BF16 (the BF16
+ * copy holds the CDF only, for precision studies).  Asynchronous on stream. */
+int32_t qed_table_to_device(qed_table* t, void* stream);
+
+void qed_table_destroy(qed_table* t);
+
+/* ---------------------------------------------------------------- context */
+typedef struct qed_context qed_context;
+
+/* Create a context on `device` (allocates ~ 16 MiB of device scratch). */
+int32_t qed_context_create(int32_t device, qed_context** out);
+void qed_context_destroy(qed_context* ctx);
+
+/* -------------------------------------------------------------- particles
+ * One species' SoA arrays in device memory, n elements of `dtype` each.
+ * tau is read and written; u is written by photon emission; w (weight,
+ * may be NULL meaning 1) is copied to products. */
+typedef struct {
+    void *ux, *uy, *uz;
+    void *ex, *ey, *ez;
+    void *bx, *by, *bz;
+    void *tau;
+    void *w;
+    int64_t n;          /* >= 0                                  */
+    int64_t id_base;    /* global id of element 0 (Philox key)   */
+    int32_t species;    /* qed_species                           */
+    int32_t dtype;      /* QED_FP64 or QED_FP32                  */
+} qed_particles;
+
+/* Product (append) buffer: products are written at slots [*count,
+ * *count + k) in parent order (tile order, then index), and *count is
+ * increased by k.  Slots >= capacity are not written but still counted, so
+ * after a call *count holds the size that was needed.  count is DEVICE
+ * memory (one int64) owned by the caller, who resets it when the products
+ * have been consumed.  parent (may be NULL) receives the parent's id. */
+typedef struct {
+    void *ux, *uy, *uz, *w, *tau;
+    int64_t* parent;
+    int64_t* count;
+    int64_t capacity;
+    int32_t dtype;      /* must equal the parents' dtype */
+    int32_t pad_;
+} qed_append;
+
+/* ------------------------------------------------------------ runtime calls */
+
+/* chi of each lepton (Sec. 2, quantum parameter of an electron or positron)
+ * or photon (chi_gamma), written to chi_out (n elements of the particles'
+ * dtype).  Evaluated as sqrt(|a|^2 + (gamma^2 - |u|^2) E_par^2)/E_s with
+ * a = gamma E_perp + c u x B, which is the printed formula rewritten so that
+ * no two O(gamma^2 E^2) terms are subtracted.  chi_mode applies to FP32. */
+int32_t qed_chi_lepton(qed_context* ctx, const qed_particles* p, int32_t chi_mode, void* chi_out,
+                       void* stream);
+int32_t qed_chi_photon(qed_context* ctx, const qed_particles* p, int32_t chi_mode, void* chi_out,
+                       void* stream);
+
+/* tau = -ln u with u the first draw of block (id, step = 2^64 - 1,
+ * species, 0): optical depth drawn from p(x) = exp(-x) (Sec. 3). */
+int32_t qed_init_optical_depth(qed_context* ctx, qed_particles* p, uint64_t seed, void* stream);
+
+/* tau <- tau - (dN/dt) dt with the BW (photons) or QS (leptons) total rate
+ * from `rate` (Sec. 2.1 / 2.2 totals, Sec. 3.1 / 3.2 interpolation), and
+ * flags[i] = (tau < 0) (may be NULL).  `rate` must match the species. */
+int32_t qed_evolve_optical_depth(qed_context* ctx, const qed_table* rate, qed_particles* p, double dt,
+                                 int32_t chi_mode, uint8_t* flags, void* stream);
+
+/* Pair creation for every photon with flags[i] != 0 (Sec. 2.1, Sec. 3.1):
+ * sample the electron's chi fraction, append the electron to `electrons`
+ * and the positron to `positrons` at the same slot, mark the photon dead
+ * (tau = +inf).  Products get tau from the block's 2nd and 3rd draws. */
+int32_t qed_generate_pairs(qed_context* ctx, const qed_table* bw, qed_particles* photons,
+                           const uint8_t* flags, uint64_t seed, uint64_t step, int32_t chi_mode,
+                           qed_append* electrons, qed_append* positrons, void* stream);
+
+/* Photon emission for every lepton with flags[i] != 0 (Sec. 2.2, Sec. 3.2):
+ * sample xi, emit a photon of energy (gamma - 1) xi along the lepton's
+ * momentum, subtract its momentum from the lepton, redraw the lepton's tau.
+ * Photons with energy below photon_min_energy (units of m_e c^2; 0 keeps
+ * all) are not appended (Sec. 5), the lepton recoils either way. */
+int32_t qed_generate_photon_and_update_momentum(qed_context* ctx, const qed_table* qs,
+                                                qed_particles* leptons, const uint8_t* flags,
+                                                uint64_t seed, uint64_t step, int32_t chi_mode,
+                                                double photon_min_energy, qed_append* photons,
+                                                void* stream);
+
+/* ------------------------------------------------------------- fused step
+ * One QED sub-step over several species in a single persistent launch:
+ * chi, rate, tau update, event test, and for events the draws, sampling,
+ * product creation, parent update and ordered append (the four steps above
+ * fused, with products appended in parent order through a decoupled
+ * look-back scan).  Leptons (electrons, positrons) emit photons into
+ * `photons`; photons create pairs into `electrons` / `positrons`; ions are
+ * passed through untouched (never read).
+ *
+ * tiles (host, may be NULL): n_tiles triples (set, begin, end) splitting
+ * set `set` of `sets` into [begin, end) ranges; products follow tile order.
+ * NULL means one tile per set, in set order.  Tiles of one set must be
+ * disjoint; tiles may not cover ions. */
+typedef struct qed_surrogate qed_surrogate;
+
+typedef struct {
+    const qed_table* bw;           /* needed if any set is a photon set   */
+    const qed_table* qs;           /* needed if any set is a lepton set   */
+    const qed_surrogate* bw_surrogate;  /* NULL: table inverse CDF        */
+    const qed_surrogate* qs_surrogate;  /* NULL: table inverse CDF        */
+    qed_particles* sets;           /* host array of n_sets descriptors    */
+    int32_t n_sets;
+    int32_t n_tiles;
+    const int64_t* tiles;          /* host, 3 * n_tiles, or NULL          */
+    qed_append* photons;           /* required if any lepton set          */
+    qed_append* electrons;         /* required if any photon set          */
+    qed_append* positrons;         /* required if any photon set          */
+    uint8_t** flags;               /* host array of n_sets device pointers (entries may be NULL), or NULL */
+    int64_t* stats;                /* device, QED_STATS_LEN int64 accumulated (may be NULL) */
+    double dt;
+    uint64_t seed;
+    uint64_t step;
+    double photon_min_energy;
+    int32_t chi_mode;
+    int32_t pad_;
+} qed_step_desc;
+
+/* stats layout (accumulated, device int64): */
+enum {
+    QED_STAT_UPDATES = 0,        /* particles updated (ions excluded)      */
+    QED_STAT_QS_EVENTS = 1,      /* lepton events                          */
+    QED_STAT_BW_EVENTS = 2,      /* photon events                          */
+    QED_STAT_PHOTONS_KEPT = 3,   /* photons appended (before capacity)     */
+    QED_STAT_SURR_BATCHES = 4,   /* event batches sampled by a surrogate   */
+    QED_STAT_SURR_FALLBACK = 5,  /* event batches that fell back to tables */
+    QED_STAT_SCAN_TIMEOUT = 7,   /* look-back waits abandoned (must stay 0) */
+    QED_STATS_LEN = 8
+};
+
+int32_t qed_step(qed_context* ctx, const qed_step_desc* desc, void* stream);
+
+/* Synchronise `stream` and read an append buffer's count to the host;
+ * returns QED_ERR_CAPACITY if it exceeds the buffer's capacity. */
+int32_t qed_read_count(const qed_append* a, int64_t* host_count, void* stream);
+
+/* ---------------------------------------------------------------- surrogate
+ * Learned inverse CDF: an MLP 2 -> 64 -> 64 -> 1 with SiLU activations,
+ * BF16 weights and FP32 accumulation, mapping (normalised ln chi, g(u)) to
+ * the sampled fraction (ln xi for QS; a scaled xi for BW), trained on
+ * samples of the table inverse CDF (Sec. 3.1 / 3.2 sampling) by the
+ * library's own BF16-MFMA forward/backward kernels and Adam.  Outside its
+ * trained chi range, or when a per-batch probe against the table exceeds
+ * `probe_tol`, sampling falls back to the table. */
+typedef struct {
+    int32_t process;        /* qed_process of the table it learns         */
+    int32_t n_samples;      /* training set size (e.g. 1 << 24)            */
+    int32_t batch;          /* minibatch (multiple of 256)                 */
+    int32_t steps;          /* optimiser steps                             */
+    float lr;               /* Adam learning rate (cosine decay to lr/100) */
+    float probe_tol;        /* allowed |delta| of the output per probe     */
+    double chi_lo, chi_hi;  /* trained chi range (inside the table range)  */
+    uint64_t seed;
+} qed_surrogate_cfg;
+
+/* Train on the device (table must be on the device).  Synchronous at the
+ * end (returns after training); *final_loss (host, may be NULL) receives
+ * the mean loss of the last 64 steps. */
+int32_t qed_surrogate_train(qed_context* ctx, const qed_table* table, const qed_surrogate_cfg* cfg,
+                            qed_surrogate** out, float* final_loss, void* stream);
+/* Build from host FP32 master weights (layout below) for tests. */
+int32_t qed_surrogate_from_host(const qed_table* table, const qed_surrogate_cfg* cfg,
+                                const float* params, qed_surrogate** out);
+/* Parameter layout (QED_SURR_NPARAM floats): W1[64][2], b1[64],
+ * W2[64][64] (row = output unit), b2[64], W3[64], b3. */
+enum { QED_SURR_NPARAM = 64 * 2 + 64 + 64 * 64 + 64 + 64 + 1 };
+int32_t qed_surrogate_get_params(const qed_surrogate* s, float* host_params);
+/* Forward on n device inputs x[n][2] (FP32) -> y[n] (FP32), BF16 MFMA. */
+int32_t qed_surrogate_forward(const qed_surrogate* s, const float* x, float* y, int64_t n, void* stream);
+/* Loss and gradient of 0.5 mean((y - t)^2) over one minibatch of device
+ * inputs x[n][2], targets t[n]; grad (device, QED_SURR_NPARAM floats) and
+ * loss (device, 1 float). */
+int32_t qed_surrogate_grad(const qed_surrogate* s, const float* x, const float* t, int64_t n,
+                           float* grad, float* loss, void* stream);
+/* Sample through the surrogate for n events: chi[n], u[n] (device, FP32)
+ * -> out[n] (device FP32: ln xi for QS, xi in [0, 1/2] for BW) with table
+ * fallback outside the trained range. */
+int32_t qed_surrogate_sample(const qed_surrogate* s, const float* chi, const float* u, float* out,
+                             int64_t n, void* stream);
+void qed_surrogate_destroy(qed_surrogate* s);
+
+/* ------------------------------------------------------------------- misc */
+const char* qed_last_error(void);
+/* Library version string. */
+const char* qed_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QEDMI_H */

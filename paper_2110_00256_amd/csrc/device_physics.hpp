@@ -1,0 +1,354 @@
+// Device-side physics of the QED step: counter-based random numbers, the
+// quantum parameter chi, table rates and inverse-CDF sampling.
+// Paper references: Sec. 2 (chi, total rates), Sec. 3.1 / 3.2 (tables,
+// interpolation, sampling), Sec. 3.3 (caller-supplied uniform numbers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "constants.hpp"
+#include "internal.hpp"
+
+namespace qedmi {
+namespace dev {
+
+// ------------------------------------------------------------------ Philox
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 64x64->128 multiplies with Weyl-sequence key bumps.
+__device__ __forceinline__ void philox4x64_10(unsigned long long& c0, unsigned long long& c1,
+                                              unsigned long long& c2, unsigned long long& c3,
+                                              unsigned long long k0, unsigned long long k1) {
+    constexpr unsigned long long kM0 = 0xD2E7470EE14C6C93ULL, kM1 = 0xCA5A826395121157ULL;
+    constexpr unsigned long long kW0 = 0x9E3779B97F4A7C15ULL, kW1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const unsigned long long lo0 = kM0 * c0, hi0 = __umul64hi(kM0, c0);
+        const unsigned long long lo1 = kM1 * c2, hi1 = __umul64hi(kM1, c2);
+        const unsigned long long n0 = hi1 ^ c1 ^ k0;
+        const unsigned long long n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += kW0;
+        k1 += kW1;
+    }
+}
+
+// (2m + 1) 2^-53 from the top 52 bits: in (0, 1), exact, and 1 - u exact.
+__device__ __forceinline__ double u01(unsigned long long w) {
+    return static_cast<double>(2ULL * (w >> 12) + 1ULL) * 0x1.0p-53;
+}
+
+struct Draws {
+    double u[4];
+};
+
+// Block `blk` of particle `id` at `step` for `species` under `seed`.
+__device__ __forceinline__ Draws draws(unsigned long long seed, unsigned long long id,
+                                       unsigned long long step, unsigned long long species,
+                                       unsigned long long blk) {
+    unsigned long long c0 = id, c1 = step, c2 = species, c3 = blk;
+    philox4x64_10(c0, c1, c2, c3, seed, 0ULL);
+    Draws d;
+    d.u[0] = u01(c0);
+    d.u[1] = u01(c1);
+    d.u[2] = u01(c2);
+    d.u[3] = u01(c3);
+    return d;
+}
+
+constexpr unsigned long long kInitStep = ~0ULL;
+
+// ------------------------------------------------------------------ chi
+// chi E_s = sqrt(|a|^2 + (gamma^2 - |u|^2) E_par^2), a = gamma E_perp + c u x B,
+// E_par = E.n, n = u/|u|; gamma^2 - |u|^2 is 1 for leptons, 0 for photons.
+// (Sec. 2 definitions of chi and chi_gamma, with gamma (E + v x B) =
+// gamma E + c u x B and gamma v.E/c = u.E.)
+struct ChiGamma {
+    double chi;
+    double gamma;
+    double u2;
+};
+
+template <bool kPhoton>
+__device__ __forceinline__ ChiGamma chi_f64(double ux, double uy, double uz, double ex, double ey,
+                                            double ez, double bx, double by, double bz) {
+    ChiGamma r;
+    const double u2 = ux * ux + uy * uy + uz * uz;
+    const double um = sqrt(u2);
+    const double g = kPhoton ? um : sqrt(1.0 + u2);
+    r.gamma = g;
+    r.u2 = u2;
+    if (um == 0.0) {
+        r.chi = kPhoton ? 0.0 : sqrt(ex * ex + ey * ey + ez * ez) * kInvEs;
+        return r;
+    }
+    const double inv = 1.0 / um;
+    const double nx = ux * inv, ny = uy * inv, nz = uz * inv;
+    const double ep = ex * nx + ey * ny + ez * nz;
+    const double ax = g * (ex - ep * nx) + kC * (uy * bz - uz * by);
+    const double ay = g * (ey - ep * ny) + kC * (uz * bx - ux * bz);
+    const double az = g * (ez - ep * nz) + kC * (ux * by - uy * bx);
+    double s = ax * ax + ay * ay + az * az;
+    if (!kPhoton) s += ep * ep;
+    r.chi = sqrt(s) * kInvEs;
+    return r;
+}
+
+// Plain FP32 evaluation of the same decomposition; fields pre-scaled by
+// 2^-60 (exact) so that gamma |E| stays inside the FP32 range.
+template <bool kPhoton>
+__device__ __forceinline__ ChiGamma chi_f32(float ux, float uy, float uz, float ex, float ey, float ez,
+                                            float bx, float by, float bz) {
+    constexpr float kScale = 0x1.0p-60f;
+    constexpr float kCs = static_cast<float>(kC);
+    constexpr double kBack = 0x1.0p60 * kInvEs;
+    ChiGamma r;
+    ex *= kScale; ey *= kScale; ez *= kScale;
+    bx *= kScale * kCs; by *= kScale * kCs; bz *= kScale * kCs;
+    const float u2 = ux * ux + uy * uy + uz * uz;
+    const float um = sqrtf(u2);
+    const float g = kPhoton ? um : sqrtf(1.0f + u2);
+    r.gamma = g;
+    r.u2 = u2;
+    if (um == 0.0f) {
+        r.chi = kPhoton ? 0.0 : static_cast<double>(sqrtf(ex * ex + ey * ey + ez * ez)) * kBack;
+        return r;
+    }
+    const float inv = 1.0f / um;
+    const float nx = ux * inv, ny = uy * inv, nz = uz * inv;
+    const float ep = ex * nx + ey * ny + ez * nz;
+    const float ax = g * (ex - ep * nx) + (uy * bz - uz * by);
+    const float ay = g * (ey - ep * ny) + (uz * bx - ux * bz);
+    const float az = g * (ez - ep * nz) + (ux * by - uy * bx);
+    float s = ax * ax + ay * ay + az * az;
+    if (!kPhoton) s += ep * ep;
+    r.chi = static_cast<double>(sqrtf(s)) * kBack;
+    return r;
+}
+
+// ------------------------------------------------------ compensated FP32
+// Double-float arithmetic (value = hi + lo, |lo| <= ulp(hi)/2) built from
+// the error-free transformations TwoSum (Knuth) and TwoProd (fma).
+struct DF {
+    float hi, lo;
+};
+__device__ __forceinline__ DF df_two_sum(float a, float b) {
+    const float s = a + b;
+    const float bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ DF df_fast_sum(float a, float b) {
+    const float s = a + b;
+    return {s, b - (s - a)};
+}
+__device__ __forceinline__ DF df_add(DF x, DF y) {
+    DF s = df_two_sum(x.hi, y.hi);
+    return df_fast_sum(s.hi, s.lo + x.lo + y.lo);
+}
+__device__ __forceinline__ DF df_neg(DF x) { return {-x.hi, -x.lo}; }
+__device__ __forceinline__ DF df_mul(DF x, DF y) {
+    const float p = x.hi * y.hi;
+    const float e = fmaf(x.hi, y.hi, -p);
+    return df_fast_sum(p, e + (x.hi * y.lo + x.lo * y.hi));
+}
+__device__ __forceinline__ DF df_from(float a) { return {a, 0.0f}; }
+__device__ __forceinline__ DF df_sqrt(DF x) {
+    if (!(x.hi > 0.0f)) return {0.0f, 0.0f};
+    const float s = sqrtf(x.hi);
+    const float p = s * s;
+    const float e = fmaf(s, s, -p);
+    const float r = ((x.hi - p) - e + x.lo) / (2.0f * s);
+    return df_fast_sum(s, r);
+}
+__device__ __forceinline__ DF df_div(DF x, DF y) {
+    const float q1 = x.hi / y.hi;
+    const DF r = df_add(x, df_neg(df_mul(df_from(q1), y)));
+    const float q2 = r.hi / y.hi;
+    return df_fast_sum(q1, q2);
+}
+
+template <bool kPhoton>
+__device__ __forceinline__ ChiGamma chi_comp32(float fux, float fuy, float fuz, float fex, float fey,
+                                               float fez, float fbx, float fby, float fbz) {
+    constexpr float kScale = 0x1.0p-60f;
+    constexpr double kBack = 0x1.0p60 * kInvEs;
+    // c as an exact float pair: c = chi_ + clo
+    constexpr float kChi = static_cast<float>(kC);
+    constexpr float kClo = static_cast<float>(kC - static_cast<double>(kChi));
+    const DF c{kChi, kClo};
+    ChiGamma r;
+    const DF ux = df_from(fux), uy = df_from(fuy), uz = df_from(fuz);
+    const DF ex = df_from(fex * kScale), ey = df_from(fey * kScale), ez = df_from(fez * kScale);
+    const DF bx = df_mul(c, df_from(fbx * kScale)), by = df_mul(c, df_from(fby * kScale)),
+             bz = df_mul(c, df_from(fbz * kScale));
+    const DF u2 = df_add(df_add(df_mul(ux, ux), df_mul(uy, uy)), df_mul(uz, uz));
+    const DF um = df_sqrt(u2);
+    const DF g = kPhoton ? um : df_sqrt(df_add(df_from(1.0f), u2));
+    r.gamma = static_cast<double>(g.hi) + static_cast<double>(g.lo);
+    r.u2 = static_cast<double>(u2.hi) + static_cast<double>(u2.lo);
+    if (um.hi == 0.0f) {
+        const DF e2 = df_add(df_add(df_mul(ex, ex), df_mul(ey, ey)), df_mul(ez, ez));
+        r.chi = kPhoton ? 0.0 : static_cast<double>(df_sqrt(e2).hi) * kBack;
+        return r;
+    }
+    const DF nx = df_div(ux, um), ny = df_div(uy, um), nz = df_div(uz, um);
+    const DF ep = df_add(df_add(df_mul(ex, nx), df_mul(ey, ny)), df_mul(ez, nz));
+    const DF ax = df_add(df_mul(g, df_add(ex, df_neg(df_mul(ep, nx)))),
+                         df_add(df_mul(uy, bz), df_neg(df_mul(uz, by))));
+    const DF ay = df_add(df_mul(g, df_add(ey, df_neg(df_mul(ep, ny)))),
+                         df_add(df_mul(uz, bx), df_neg(df_mul(ux, bz))));
+    const DF az = df_add(df_mul(g, df_add(ez, df_neg(df_mul(ep, nz)))),
+                         df_add(df_mul(ux, by), df_neg(df_mul(uy, bx))));
+    DF s = df_add(df_add(df_mul(ax, ax), df_mul(ay, ay)), df_mul(az, az));
+    if (!kPhoton) s = df_add(s, df_mul(ep, ep));
+    const DF rt = df_sqrt(s);
+    r.chi = (static_cast<double>(rt.hi) + static_cast<double>(rt.lo)) * kBack;
+    return r;
+}
+
+// Dispatch on element type and chi mode.  FP64 data always uses FP64.
+template <typename T, bool kPhoton>
+__device__ __forceinline__ ChiGamma chi_of(int chi_mode, T ux, T uy, T uz, T ex, T ey, T ez, T bx, T by,
+                                           T bz) {
+    if constexpr (sizeof(T) == 8) {
+        return chi_f64<kPhoton>(ux, uy, uz, ex, ey, ez, bx, by, bz);
+    } else {
+        if (chi_mode == QED_CHI_FP32) return chi_f32<kPhoton>(ux, uy, uz, ex, ey, ez, bx, by, bz);
+        if (chi_mode == QED_CHI_COMP32) return chi_comp32<kPhoton>(ux, uy, uz, ex, ey, ez, bx, by, bz);
+        return chi_f64<kPhoton>(ux, uy, uz, ex, ey, ez, bx, by, bz);
+    }
+}
+
+// ------------------------------------------------------------------ rates
+// Precision-generic helpers.
+__device__ __forceinline__ double dlog(double x) { return log(x); }
+__device__ __forceinline__ float dlog(float x) { return logf(x); }
+__device__ __forceinline__ double dexp(double x) { return exp(x); }
+__device__ __forceinline__ float dexp(float x) { return expf(x); }
+
+// Interval index n in [0, N-2] and weight f = t - n for ln chi on the grid.
+template <typename T>
+__device__ __forceinline__ void grid_pos(const TableDev& t, T lnchi, int& n, T& f) {
+    const T x = (lnchi - static_cast<T>(t.ln_chi_min)) * static_cast<T>(t.inv_dlnchi);
+    int k = static_cast<int>(floor(x));
+    k = k < 0 ? 0 : (k > t.n_chi - 2 ? t.n_chi - 2 : k);
+    n = k;
+    f = x - static_cast<T>(k);
+}
+
+// BW: dN/dt = (alpha m c^2/hbar) (chi_gamma/gamma_gamma) T(chi_gamma)
+// (Sec. 2.1); ln T interpolated linearly in ln chi (Sec. 3.1); outside the
+// table, the asymptotes of the integral definition matched at the edges:
+// ln T - (8/3)(1/chi - 1/chi_min) below, ln T - (1/3) ln(chi/chi_max) above.
+template <typename T>
+__device__ __forceinline__ T rate_bw(const T* ln_t, const TableDev& t, T chi, T gamma_g) {
+    if (!(chi > T(0)) || !(gamma_g > T(0))) return T(0);
+    T y;
+    if (chi < static_cast<T>(t.chi_min)) {
+        y = ln_t[0] - T(8.0 / 3.0) * (T(1) / chi - static_cast<T>(1.0 / t.chi_min));
+    } else if (chi > static_cast<T>(t.chi_max)) {
+        y = ln_t[t.n_chi - 1] - T(1.0 / 3.0) * (dlog(chi) - static_cast<T>(log(t.chi_max)));
+    } else {
+        int n;
+        T f;
+        grid_pos<T>(t, dlog(chi), n, f);
+        y = ln_t[n] + f * (ln_t[n + 1] - ln_t[n]);
+    }
+    return static_cast<T>(kRateR0) * (chi / gamma_g) * dexp(y);
+}
+
+// QS: dN/dt = (2/3)(alpha m c^2/hbar) G(chi)/gamma (Sec. 2.2); ln G
+// interpolated in ln chi; first/last stored value outside (Sec. 3.2).
+template <typename T>
+__device__ __forceinline__ T rate_qs(const T* ln_g, const TableDev& t, T chi, T gamma) {
+    T y;
+    if (!(chi >= static_cast<T>(t.chi_min))) {
+        y = ln_g[0];
+    } else if (chi > static_cast<T>(t.chi_max)) {
+        y = ln_g[t.n_chi - 1];
+    } else {
+        int n;
+        T f;
+        grid_pos<T>(t, dlog(chi), n, f);
+        y = ln_g[n] + f * (ln_g[n + 1] - ln_g[n]);
+    }
+    return static_cast<T>(2.0 / 3.0 * kRateR0) * dexp(y) / gamma;
+}
+
+// Row position for the 2D tables: chi clamped to [chi_min, chi_max].
+template <typename T>
+__device__ __forceinline__ void row_pos(const TableDev& t, T chi, int& n, T& f) {
+    T c = chi;
+    if (!(c >= static_cast<T>(t.chi_min))) c = static_cast<T>(t.chi_min);
+    if (c > static_cast<T>(t.chi_max)) c = static_cast<T>(t.chi_max);
+    grid_pos<T>(t, dlog(c), n, f);
+}
+
+template <typename T>
+__device__ __forceinline__ const T* cdf_ptr(const TableDev& t);
+template <>
+__device__ __forceinline__ const double* cdf_ptr<double>(const TableDev& t) { return t.cdf64; }
+template <>
+__device__ __forceinline__ const float* cdf_ptr<float>(const TableDev& t) { return t.cdf32; }
+
+// BW pair sampling (Sec. 3.1): r <= 1/2 selects the electron, otherwise
+// r -> 1 - r selects the positron; rows n, n+1 interpolated in ln chi_gamma;
+// binary search for P_m <= r < P_{m+1}; linear inverse in xi.
+template <typename T>
+__device__ __forceinline__ T sample_bw(const TableDev& t, T chi, T r, bool& electron) {
+    int n;
+    T f;
+    row_pos<T>(t, chi, n, f);
+    electron = (r <= T(0.5));
+    if (!electron) r = T(1) - r;
+    const int nf = t.n_frac;
+    const T* p0 = cdf_ptr<T>(t) + static_cast<size_t>(n) * nf;
+    const T* p1 = p0 + nf;
+    int lo = 0, hi = nf - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        const T pm = p0[mid] + f * (p1[mid] - p0[mid]);
+        if (pm <= r) lo = mid; else hi = mid;
+    }
+    const T pa = p0[lo] + f * (p1[lo] - p0[lo]);
+    const T pb = p0[lo + 1] + f * (p1[lo + 1] - p0[lo + 1]);
+    const T scale = T(0.5) / static_cast<T>(nf - 1);
+    const T xa = scale * static_cast<T>(lo), xb = scale * static_cast<T>(lo + 1);
+    return xa + (r - pa) * (xb - xa) / (pb - pa);
+}
+
+// QS photon sampling (Sec. 3.2): ln P rows interpolated in ln chi; binary
+// search on ln r; log-log inverse.  Below the first knot the small-xi law
+// P ~ xi^{1/3} continues the table: ln xi = ln xi_min + 3 (ln r - ln P_0).
+// Returns ln xi.
+template <typename T>
+__device__ __forceinline__ T sample_qs_lnxi(const TableDev& t, T chi, T r) {
+    int n;
+    T f;
+    row_pos<T>(t, chi, n, f);
+    const int nf = t.n_frac;
+    const T* p0 = cdf_ptr<T>(t) + static_cast<size_t>(n) * nf;
+    const T* p1 = p0 + nf;
+    const T lr = dlog(r);
+    const T lmin = static_cast<T>(t.ln_frac_min);
+    const T l0 = p0[0] + f * (p1[0] - p0[0]);
+    if (lr < l0) return lmin + T(3) * (lr - l0);
+    int lo = 0, hi = nf - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        const T lm = p0[mid] + f * (p1[mid] - p0[mid]);
+        if (lm <= lr) lo = mid; else hi = mid;
+    }
+    const T la = p0[lo] + f * (p1[lo] - p0[lo]);
+    const T lb = p0[lo + 1] + f * (p1[lo + 1] - p0[lo + 1]);
+    const T inv = T(1) / static_cast<T>(nf - 1);
+    const T xa = lmin * (T(1) - static_cast<T>(lo) * inv);
+    const T xb = lmin * (T(1) - static_cast<T>(lo + 1) * inv);
+    return xa + (lr - la) * (xb - xa) / (lb - la);
+}
+
+}  // namespace dev
+}  // namespace qedmi

@@ -1,0 +1,129 @@
+// Internal structures shared by the C-ABI layer (api.cpp, table.cpp) and
+// the HIP kernels (step.hip, surrogate.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/qedmi.h"
+
+namespace qedmi {
+
+constexpr int kMaxSets = 8;
+constexpr int kBlock = 256;               // threads per block of the step kernels
+constexpr int kChunk = 4096;              // particles per chunk (16 per thread)
+constexpr int kMaxTableChi = 1024;        // 1D table points staged in LDS
+constexpr int kStatusBits = 30;           // value bits of a look-back status word
+
+void set_error(const std::string& msg);
+
+// Device view of one lookup table ("table view": non-owning pointers passed
+// by value to kernels).
+struct TableDev {
+    const double* ln_rate64;
+    const double* cdf64;
+    const float* ln_rate32;
+    const float* cdf32;
+    const uint16_t* cdf16;
+    int32_t n_chi, n_frac;
+    double chi_min, chi_max;
+    double ln_chi_min, inv_dlnchi;   // t = (ln chi - ln chi_min) * inv_dlnchi
+    double frac_min, ln_frac_min;
+};
+
+struct SetDev {
+    void* p[11];          // ux uy uz ex ey ez bx by bz tau w
+    int64_t n, id_base;
+    int32_t species;
+    int32_t stream;       // 0: emits photons (leptons), 1: makes pairs (photons), -1: ions
+    uint8_t* flags;
+};
+
+struct AppendDev {
+    void *ux, *uy, *uz, *w, *tau;
+    int64_t* parent;
+    int64_t* count;
+    int64_t capacity;
+};
+
+// One chunk of <= kChunk consecutive particles of one set.  Chunks are
+// ordered by (stream, tile order); each stream's chunks are contiguous.
+struct ChunkDesc {
+    int64_t begin;
+    int32_t set;
+    int32_t len;
+    int32_t stream;
+    int32_t stream_first;   // index of the first chunk of this stream
+    int32_t stream_last;    // index of the last chunk of this stream
+    int32_t pad_;
+};
+
+struct SurrogateDev;   // defined in surrogate.hpp
+
+struct StepArgs {
+    SetDev sets[kMaxSets];
+    int32_t n_sets;
+    int32_t n_chunks;
+    const ChunkDesc* chunks;
+    unsigned long long* status;   // look-back status words, one per chunk
+    unsigned long long* ticket;   // monotonically increasing chunk ticket
+    unsigned long long ticket_base;
+    uint32_t epoch;               // launch tag carried by status words
+    int32_t generate_only;        // 1: events from flags, no evolution
+    TableDev bw, qs;
+    AppendDev ph, el, po;
+    int64_t* stats;
+    const SurrogateDev* bw_surr;  // device pointers, may be null
+    const SurrogateDev* qs_surr;
+    double dt;
+    unsigned long long seed, step;
+    double photon_min_energy;
+    int32_t chi_mode;
+};
+
+struct ElemArgs {
+    SetDev set;
+    TableDev table;
+    void* chi_out;
+    double dt;
+    unsigned long long seed;
+    int32_t chi_mode;
+    int32_t is_photon;
+};
+
+// Kernel launchers (step.hip).  Return hipError_t of the launch.
+hipError_t launch_step(const StepArgs& a, int dtype, int grid, hipStream_t s);
+hipError_t launch_chi(const ElemArgs& a, int dtype, hipStream_t s);
+hipError_t launch_init_tau(const ElemArgs& a, int dtype, hipStream_t s);
+hipError_t launch_evolve(const ElemArgs& a, int dtype, hipStream_t s);
+int step_grid_size(int dtype, int device);
+
+}  // namespace qedmi
+
+struct qed_table {
+    qed_table_params p{};
+    std::vector<double> ln_rate, cdf;
+    int device = -1;
+    double* d_ln_rate64 = nullptr;
+    double* d_cdf64 = nullptr;
+    float* d_ln_rate32 = nullptr;
+    float* d_cdf32 = nullptr;
+    uint16_t* d_cdf16 = nullptr;
+    qedmi::TableDev view() const;
+};
+
+struct qed_context {
+    int device = -1;
+    int cu_count = 0;
+    unsigned long long* d_ticket = nullptr;
+    unsigned long long* d_status = nullptr;
+    int64_t status_cap = 0;
+    unsigned long long ticket_issued = 0;   // host mirror of the ticket counter
+    uint32_t epoch = 0;
+    qedmi::ChunkDesc* d_chunks = nullptr;
+    int64_t chunks_cap = 0;
+    std::vector<qedmi::ChunkDesc> h_chunks_cached;
+};

@@ -1,0 +1,481 @@
+// HIP kernels of the QED sub-step for gfx950 (MI355X).
+//
+// step_kernel: one persistent launch processes chunks of kChunk particles
+// taken from an atomic ticket counter.  For each chunk:
+//   phase 1  stream the particle SoA (coalesced), compute chi, the total rate
+//            from the 1D table staged in LDS, tau <- tau - rate dt, and the
+//            event predicate tau < 0 (paper Fig. 1, Sec. 3); each wave's
+//            events are recorded as a 64-bit ballot mask in LDS;
+//   list     the masks are prefix-summed (one wave) and expanded with mbcnt
+//            into an ordered list of event indices (dense event processing:
+//            events of the whole chunk are handed to consecutive lanes);
+//   scan     the chunk's product count is published and the exclusive
+//            prefix over earlier chunks of the same product stream obtained
+//            by decoupled look-back (Merrill & Garland 2016); tickets are
+//            taken in chunk order, so every predecessor is already running;
+//   phase 2  each event: Philox draws, inverse-CDF sample (table or MLP
+//            surrogate), product kinematics (Sec. 2.1, 2.2), parent update,
+//            products written at deterministic slots in parent order.
+#include <hip/hip_runtime.h>
+
+#include "device_physics.hpp"
+#include "internal.hpp"
+#include "surrogate.hpp"
+
+namespace qedmi {
+
+namespace {
+
+constexpr unsigned kFlagA = 1u, kFlagP = 2u;
+constexpr unsigned long long kValueMask = (1ULL << kStatusBits) - 1ULL;
+constexpr int kSpinLimit = 1 << 24;
+
+__device__ __forceinline__ unsigned long long pack_status(uint32_t epoch, unsigned flag,
+                                                          unsigned long long v) {
+    return (static_cast<unsigned long long>(epoch) << 32) | (static_cast<unsigned long long>(flag) << 30) |
+           (v & kValueMask);
+}
+
+template <typename T>
+__device__ __forceinline__ T ld(const void* p, int64_t i) {
+    return static_cast<const T*>(p)[i];
+}
+template <typename T>
+__device__ __forceinline__ void st(void* p, int64_t i, T v) {
+    static_cast<T*>(p)[i] = v;
+}
+
+template <typename T>
+__device__ __forceinline__ const T* ln_rate_ptr(const TableDev& t);
+template <>
+__device__ __forceinline__ const double* ln_rate_ptr<double>(const TableDev& t) { return t.ln_rate64; }
+template <>
+__device__ __forceinline__ const float* ln_rate_ptr<float>(const TableDev& t) { return t.ln_rate32; }
+
+__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+
+// number of set bits of `mask` below this lane
+__device__ __forceinline__ unsigned bits_below(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi(static_cast<unsigned>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<unsigned>(mask), 0u));
+}
+
+// Decoupled look-back for chunk k with aggregate agg; returns the exclusive
+// prefix over earlier chunks of its stream.  Called by one thread.
+__device__ long long look_back(const StepArgs& a, int k, const ChunkDesc& c, unsigned long long agg,
+                               int64_t* err) {
+    unsigned long long* st_k = a.status + k;
+    if (k == c.stream_first) {
+        __hip_atomic_store(st_k, pack_status(a.epoch, kFlagP, agg), __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        return 0;
+    }
+    __hip_atomic_store(st_k, pack_status(a.epoch, kFlagA, agg), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    long long excl = 0;
+    int j = k - 1;
+    int spins = 0;
+    while (j >= c.stream_first) {
+        const unsigned long long v =
+            __hip_atomic_load(a.status + j, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned flag = static_cast<unsigned>(v >> 30) & 3u;
+        if (static_cast<uint32_t>(v >> 32) != a.epoch || flag == 0u) {
+            if (++spins > kSpinLimit) {   // predecessor never published: give up, report
+                if (err) atomicAdd(reinterpret_cast<unsigned long long*>(err), 1ULL);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        excl += static_cast<long long>(v & kValueMask);
+        if (flag == kFlagP) break;
+        --j;
+    }
+    __hip_atomic_store(st_k, pack_status(a.epoch, kFlagP, static_cast<unsigned long long>(excl) + agg),
+                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return excl;
+}
+
+template <typename T>
+__device__ __forceinline__ void write_product(const AppendDev& o, int64_t slot, T ux, T uy, T uz, T w, T tau,
+                                              int64_t parent) {
+    if (slot >= o.capacity) return;
+    st<T>(o.ux, slot, ux);
+    st<T>(o.uy, slot, uy);
+    st<T>(o.uz, slot, uz);
+    st<T>(o.w, slot, w);
+    st<T>(o.tau, slot, tau);
+    if (o.parent) o.parent[slot] = parent;
+}
+
+// Sampled photon fraction for a lepton event (ln xi): table or surrogate.
+template <typename T>
+__device__ __forceinline__ T qs_lnxi(const StepArgs& a, T chi, T r) {
+    return dev::sample_qs_lnxi<T>(a.qs, chi, r);
+}
+
+// Per-event state shared by the two passes over a chunk's events.
+template <typename T>
+struct EventCtx {
+    int64_t j;          // particle index in the set
+    T ux, uy, uz;
+    double chi, gamma, u2;
+    dev::Draws d;
+};
+
+template <typename T, bool kPhoton>
+__device__ __forceinline__ EventCtx<T> load_event(const StepArgs& a, const SetDev& S, int64_t j) {
+    EventCtx<T> e;
+    e.j = j;
+    e.ux = ld<T>(S.p[0], j);
+    e.uy = ld<T>(S.p[1], j);
+    e.uz = ld<T>(S.p[2], j);
+    const dev::ChiGamma cg = dev::chi_of<T, kPhoton>(a.chi_mode, e.ux, e.uy, e.uz, ld<T>(S.p[3], j),
+                                                     ld<T>(S.p[4], j), ld<T>(S.p[5], j), ld<T>(S.p[6], j),
+                                                     ld<T>(S.p[7], j), ld<T>(S.p[8], j));
+    e.chi = cg.chi;
+    e.gamma = cg.gamma;
+    e.u2 = cg.u2;
+    e.d = dev::draws(a.seed, static_cast<unsigned long long>(S.id_base + j), a.step,
+                     static_cast<unsigned long long>(S.species), 0ULL);
+    return e;
+}
+
+// QS photon energy gamma_gamma = (gamma - 1) xi, with gamma - 1 = |u|^2/(gamma + 1).
+template <typename T>
+__device__ __forceinline__ T qs_photon_energy(const StepArgs& a, const EventCtx<T>& e, T& xi_out) {
+    const T lnxi = qs_lnxi<T>(a, static_cast<T>(e.chi), static_cast<T>(e.d.u[0]));
+    const T xi = dev::dexp(lnxi);
+    xi_out = xi;
+    return static_cast<T>(e.u2 / (e.gamma + 1.0)) * xi;
+}
+
+template <typename T, int kChiMode>
+__global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int nbw = a.bw.n_chi > 0 ? a.bw.n_chi : 0;
+    const int nqs = a.qs.n_chi > 0 ? a.qs.n_chi : 0;
+    T* t_bw = reinterpret_cast<T*>(lds_raw);
+    T* t_qs = t_bw + ((nbw + 1) & ~1);
+    uint16_t* evlist = reinterpret_cast<uint16_t*>(t_qs + ((nqs + 1) & ~1));
+    __shared__ unsigned long long emask[kChunk / 64];
+    __shared__ unsigned long long kmask[kChunk / 64];
+    __shared__ int epref[kChunk / 64];
+    __shared__ int kpref[kChunk / 64];
+    __shared__ int s_ticket, s_total, s_kept;
+    __shared__ long long s_excl, s_base0, s_base1;
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const unsigned lane = lane_id();
+
+    if (a.bw.ln_rate64 || a.bw.ln_rate32)
+        for (int i = tid; i < nbw; i += kBlock) t_bw[i] = ln_rate_ptr<T>(a.bw)[i];
+    if (a.qs.ln_rate64 || a.qs.ln_rate32)
+        for (int i = tid; i < nqs; i += kBlock) t_qs[i] = ln_rate_ptr<T>(a.qs)[i];
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_ticket = static_cast<int>(atomicAdd(a.ticket, 1ULL) - a.ticket_base);
+        __syncthreads();
+        const int k = s_ticket;
+        if (k >= a.n_chunks) break;
+        const ChunkDesc c = a.chunks[k];
+        const SetDev& S = a.sets[c.set];
+        const bool photon = (c.stream == 1);
+        if (tid == 0) {
+            if (photon) {
+                s_base0 = *a.el.count;
+                s_base1 = *a.po.count;
+            } else {
+                s_base0 = *a.ph.count;
+                s_base1 = 0;
+            }
+        }
+
+        // ---------------- phase 1: stream, evolve, flag
+        const T dt = static_cast<T>(a.dt);
+        for (int it = 0; it < kChunk / kBlock; ++it) {
+            const int loc = it * kBlock + tid;
+            bool ev = false;
+            if (loc < c.len) {
+                const int64_t j = c.begin + loc;
+                if (a.generate_only) {
+                    ev = S.flags[j] != 0;
+                } else {
+                    const T ux = ld<T>(S.p[0], j), uy = ld<T>(S.p[1], j), uz = ld<T>(S.p[2], j);
+                    const T ex = ld<T>(S.p[3], j), ey = ld<T>(S.p[4], j), ez = ld<T>(S.p[5], j);
+                    const T bx = ld<T>(S.p[6], j), by = ld<T>(S.p[7], j), bz = ld<T>(S.p[8], j);
+                    const T tau = ld<T>(S.p[9], j);
+                    T rate;
+                    if (photon) {
+                        const dev::ChiGamma cg = dev::chi_of<T, true>(kChiMode, ux, uy, uz, ex, ey, ez, bx, by, bz);
+                        rate = dev::rate_bw<T>(t_bw, a.bw, static_cast<T>(cg.chi), static_cast<T>(cg.gamma));
+                    } else {
+                        const dev::ChiGamma cg = dev::chi_of<T, false>(kChiMode, ux, uy, uz, ex, ey, ez, bx, by, bz);
+                        rate = dev::rate_qs<T>(t_qs, a.qs, static_cast<T>(cg.chi), static_cast<T>(cg.gamma));
+                    }
+                    const T tn = tau - rate * dt;
+                    ev = tn < T(0);
+                    if (!ev) st<T>(S.p[9], j, tn);
+                    if (S.flags) S.flags[j] = static_cast<uint8_t>(ev);
+                }
+            }
+            const unsigned long long m = __ballot(ev);
+            if (lane == 0) emask[it * (kBlock / 64) + wave] = m;
+        }
+        __syncthreads();
+
+        // ---------------- ordered event list
+        if (wave == 0) {
+            const int cnt = __popcll(emask[lane]);
+            int incl = cnt;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int v = __shfl_up(incl, o);
+                if (static_cast<int>(lane) >= o) incl += v;
+            }
+            epref[lane] = incl - cnt;
+            if (lane == 63) s_total = incl;
+        }
+        __syncthreads();
+        for (int w = wave; w < kChunk / 64; w += kBlock / 64) {
+            const unsigned long long m = emask[w];
+            if ((m >> lane) & 1ULL) evlist[epref[w] + bits_below(m)] = static_cast<uint16_t>(w * 64 + lane);
+        }
+        const int total = s_total;
+        __syncthreads();
+
+        // ---------------- product count (photons below threshold are dropped)
+        const bool thresh = !photon && a.photon_min_energy > 0.0;
+        if (thresh) {
+            for (int e0 = 0; e0 < total; e0 += kBlock) {
+                const int e = e0 + tid;
+                bool keep = false;
+                if (e < total) {
+                    const EventCtx<T> ec = load_event<T, false>(a, S, c.begin + evlist[e]);
+                    T xi;
+                    keep = qs_photon_energy<T>(a, ec, xi) >= static_cast<T>(a.photon_min_energy);
+                }
+                const unsigned long long m = __ballot(keep);
+                if (lane == 0) kmask[(e0 >> 6) + wave] = m;
+            }
+            __syncthreads();
+            if (wave == 0) {
+                const int nm = (total + 63) >> 6;
+                const int cnt = static_cast<int>(lane) < nm ? __popcll(kmask[lane]) : 0;
+                int incl = cnt;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int v = __shfl_up(incl, o);
+                    if (static_cast<int>(lane) >= o) incl += v;
+                }
+                kpref[lane] = incl - cnt;
+                if (lane == 63) s_kept = incl;
+            }
+            __syncthreads();
+        }
+        const int prods = thresh ? s_kept : total;
+
+        // ---------------- decoupled look-back over the chunk's stream
+        if (tid == 0) {
+            s_excl = look_back(a, k, c, static_cast<unsigned long long>(prods),
+                               a.stats ? a.stats + QED_STAT_SCAN_TIMEOUT : nullptr);
+            const long long incl = s_excl + prods;
+            if (k == c.stream_last) {
+                if (photon) {
+                    *a.el.count = s_base0 + incl;
+                    *a.po.count = s_base1 + incl;
+                } else {
+                    *a.ph.count = s_base0 + incl;
+                }
+            }
+            if (a.stats) {
+                atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + QED_STAT_UPDATES),
+                          static_cast<unsigned long long>(c.len));
+                atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + (photon ? QED_STAT_BW_EVENTS
+                                                                                 : QED_STAT_QS_EVENTS)),
+                          static_cast<unsigned long long>(total));
+                if (!photon)
+                    atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + QED_STAT_PHOTONS_KEPT),
+                              static_cast<unsigned long long>(prods));
+            }
+        }
+        __syncthreads();
+        const long long slot0 = s_excl;
+
+        // ---------------- phase 2: events
+        for (int e0 = 0; e0 < total; e0 += kBlock) {
+            const int e = e0 + tid;
+            if (e < total) {
+                const int64_t j = c.begin + evlist[e];
+                const int64_t parent = S.id_base + j;
+                const T w = S.p[10] ? ld<T>(S.p[10], j) : T(1);
+                if (photon) {
+                    const EventCtx<T> ec = load_event<T, true>(a, S, j);
+                    bool esel;
+                    const T xi = dev::sample_bw<T>(a.bw, static_cast<T>(ec.chi), static_cast<T>(ec.d.u[0]), esel);
+                    const T sx = xi * ec.ux, sy = xi * ec.uy, sz = xi * ec.uz;
+                    const T ox = ec.ux - sx, oy = ec.uy - sy, oz = ec.uz - sz;
+                    const T te = static_cast<T>(-log(ec.d.u[1]));
+                    const T tp = static_cast<T>(-log(ec.d.u[2]));
+                    const long long slot = slot0 + e;
+                    if (esel) {
+                        write_product<T>(a.el, s_base0 + slot, sx, sy, sz, w, te, parent);
+                        write_product<T>(a.po, s_base1 + slot, ox, oy, oz, w, tp, parent);
+                    } else {
+                        write_product<T>(a.el, s_base0 + slot, ox, oy, oz, w, te, parent);
+                        write_product<T>(a.po, s_base1 + slot, sx, sy, sz, w, tp, parent);
+                    }
+                    st<T>(S.p[9], j, static_cast<T>(__builtin_inf()));
+                } else {
+                    const EventCtx<T> ec = load_event<T, false>(a, S, j);
+                    T xi;
+                    const T gg = qs_photon_energy<T>(a, ec, xi);
+                    const T um = static_cast<T>(sqrt(ec.u2));
+                    const T s = um > T(0) ? gg / um : T(0);
+                    const T px = s * ec.ux, py = s * ec.uy, pz = s * ec.uz;
+                    st<T>(S.p[0], j, ec.ux - px);
+                    st<T>(S.p[1], j, ec.uy - py);
+                    st<T>(S.p[2], j, ec.uz - pz);
+                    st<T>(S.p[9], j, static_cast<T>(-log(ec.d.u[1])));
+                    bool keep = true;
+                    long long rank = e;
+                    if (thresh) {
+                        const unsigned long long m = kmask[e >> 6];
+                        keep = (m >> (e & 63)) & 1ULL;
+                        rank = kpref[e >> 6] + __popcll(m & ((1ULL << (e & 63)) - 1ULL));
+                    }
+                    if (keep)
+                        write_product<T>(a.ph, s_base0 + slot0 + rank, px, py, pz, w,
+                                         static_cast<T>(-log(ec.d.u[2])), parent);
+                }
+            }
+        }
+    }
+}
+
+// Elementwise kernels (grid-stride) -----------------------------------------
+template <typename T, bool kPhoton>
+__global__ void __launch_bounds__(256) chi_kernel(ElemArgs a) {
+    const SetDev& S = a.set;
+    for (int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; j < S.n;
+         j += int64_t(gridDim.x) * blockDim.x) {
+        const dev::ChiGamma cg = dev::chi_of<T, kPhoton>(a.chi_mode, ld<T>(S.p[0], j), ld<T>(S.p[1], j),
+                                                         ld<T>(S.p[2], j), ld<T>(S.p[3], j), ld<T>(S.p[4], j),
+                                                         ld<T>(S.p[5], j), ld<T>(S.p[6], j), ld<T>(S.p[7], j),
+                                                         ld<T>(S.p[8], j));
+        st<T>(a.chi_out, j, static_cast<T>(cg.chi));
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) init_tau_kernel(ElemArgs a) {
+    const SetDev& S = a.set;
+    for (int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; j < S.n;
+         j += int64_t(gridDim.x) * blockDim.x) {
+        const dev::Draws d = dev::draws(a.seed, static_cast<unsigned long long>(S.id_base + j), dev::kInitStep,
+                                        static_cast<unsigned long long>(S.species), 0ULL);
+        st<T>(S.p[9], j, static_cast<T>(-log(d.u[0])));
+    }
+}
+
+template <typename T, bool kPhoton>
+__global__ void __launch_bounds__(256) evolve_kernel(ElemArgs a) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* tab = reinterpret_cast<T*>(lds_raw);
+    for (int i = threadIdx.x; i < a.table.n_chi; i += blockDim.x) tab[i] = ln_rate_ptr<T>(a.table)[i];
+    __syncthreads();
+    const SetDev& S = a.set;
+    const T dt = static_cast<T>(a.dt);
+    for (int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; j < S.n;
+         j += int64_t(gridDim.x) * blockDim.x) {
+        const dev::ChiGamma cg = dev::chi_of<T, kPhoton>(a.chi_mode, ld<T>(S.p[0], j), ld<T>(S.p[1], j),
+                                                         ld<T>(S.p[2], j), ld<T>(S.p[3], j), ld<T>(S.p[4], j),
+                                                         ld<T>(S.p[5], j), ld<T>(S.p[6], j), ld<T>(S.p[7], j),
+                                                         ld<T>(S.p[8], j));
+        const T rate = kPhoton ? dev::rate_bw<T>(tab, a.table, static_cast<T>(cg.chi), static_cast<T>(cg.gamma))
+                               : dev::rate_qs<T>(tab, a.table, static_cast<T>(cg.chi), static_cast<T>(cg.gamma));
+        const T tn = ld<T>(S.p[9], j) - rate * dt;
+        st<T>(S.p[9], j, tn);
+        if (S.flags) S.flags[j] = static_cast<uint8_t>(tn < T(0));
+    }
+}
+
+size_t step_lds_bytes(const StepArgs& a, size_t elem) {
+    const int nbw = a.bw.n_chi > 0 ? a.bw.n_chi : 0;
+    const int nqs = a.qs.n_chi > 0 ? a.qs.n_chi : 0;
+    return elem * (((nbw + 1) & ~1) + ((nqs + 1) & ~1)) + sizeof(uint16_t) * kChunk;
+}
+
+template <typename T>
+hipError_t launch_step_t(const StepArgs& a, int grid, hipStream_t s) {
+    const size_t lds = step_lds_bytes(a, sizeof(T));
+    if (a.chi_mode == QED_CHI_COMP32)
+        hipLaunchKernelGGL((step_kernel<T, QED_CHI_COMP32>), dim3(grid), dim3(kBlock), lds, s, a);
+    else if (a.chi_mode == QED_CHI_FP32)
+        hipLaunchKernelGGL((step_kernel<T, QED_CHI_FP32>), dim3(grid), dim3(kBlock), lds, s, a);
+    else
+        hipLaunchKernelGGL((step_kernel<T, QED_CHI_FP64>), dim3(grid), dim3(kBlock), lds, s, a);
+    return hipGetLastError();
+}
+
+int elem_grid(int64_t n) {
+    const int64_t b = (n + 255) / 256;
+    return static_cast<int>(b < 1 ? 1 : (b > 65536 ? 65536 : b));
+}
+
+}  // namespace
+
+hipError_t launch_step(const StepArgs& a, int dtype, int grid, hipStream_t s) {
+    return dtype == QED_FP64 ? launch_step_t<double>(a, grid, s) : launch_step_t<float>(a, grid, s);
+}
+
+int step_grid_size(int dtype, int device) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
+        cus = 256;
+    int per_cu = 0;
+    hipError_t e;
+    if (dtype == QED_FP64)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_kernel<double, QED_CHI_FP64>, kBlock,
+                                                         sizeof(double) * 2 * kMaxTableChi + 2 * kChunk);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_kernel<float, QED_CHI_FP64>, kBlock,
+                                                         sizeof(float) * 2 * kMaxTableChi + 2 * kChunk);
+    if (e != hipSuccess || per_cu <= 0) per_cu = 4;
+    return cus * per_cu;
+}
+
+hipError_t launch_chi(const ElemArgs& a, int dtype, hipStream_t s) {
+    const int g = elem_grid(a.set.n);
+    if (dtype == QED_FP64) {
+        if (a.is_photon) hipLaunchKernelGGL((chi_kernel<double, true>), dim3(g), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((chi_kernel<double, false>), dim3(g), dim3(256), 0, s, a);
+    } else {
+        if (a.is_photon) hipLaunchKernelGGL((chi_kernel<float, true>), dim3(g), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((chi_kernel<float, false>), dim3(g), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_init_tau(const ElemArgs& a, int dtype, hipStream_t s) {
+    const int g = elem_grid(a.set.n);
+    if (dtype == QED_FP64) hipLaunchKernelGGL((init_tau_kernel<double>), dim3(g), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((init_tau_kernel<float>), dim3(g), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_evolve(const ElemArgs& a, int dtype, hipStream_t s) {
+    const int g = std::min(elem_grid(a.set.n), 2048);
+    const size_t lds = (dtype == QED_FP64 ? 8 : 4) * static_cast<size_t>(a.table.n_chi);
+    if (dtype == QED_FP64) {
+        if (a.is_photon) hipLaunchKernelGGL((evolve_kernel<double, true>), dim3(g), dim3(256), lds, s, a);
+        else hipLaunchKernelGGL((evolve_kernel<double, false>), dim3(g), dim3(256), lds, s, a);
+    } else {
+        if (a.is_photon) hipLaunchKernelGGL((evolve_kernel<float, true>), dim3(g), dim3(256), lds, s, a);
+        else hipLaunchKernelGGL((evolve_kernel<float, false>), dim3(g), dim3(256), lds, s, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace qedmi

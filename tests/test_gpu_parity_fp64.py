@@ -1,0 +1,249 @@
+"""FP64 HIP path against the FP64 oracle on the same seeded inputs.
+
+Bar: event flags, product counts and parent indices bit-exact; momenta and
+optical depths within 1e-12 relative (scale max(|value|, 1) for tau and the
+parent's |u| for momenta).  Each side generates its own tables (independent
+quadratures that agree to ~1e-14)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import paper_2110_00256_amd as Q  # noqa: E402
+import qed_inputs as QI  # noqa: E402
+from oracle import oracle as O  # noqa: E402
+from tests.gpu_util import compare_append, dev_pop, host, lib_tables, oracle_tables, rel_close  # noqa: E402
+
+RTOL = 1e-12
+C1_BW = (1e-3, 1e2)
+C1_QS = (1e-3, 1e2)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return Q.Context(0)
+
+
+@pytest.fixture(scope="module")
+def tabs():
+    return lib_tables(C1_BW, C1_QS, 64, 64), oracle_tables(C1_BW, C1_QS, 64, 64)
+
+
+def _fields(pop):
+    return {k: pop[k] for k in QI.FIELDS}
+
+
+def test_chi_matches_oracle(ctx):
+    for pop, photon in ((QI.plane_wave_counter(3000, 4, False), False),
+                        (QI.plane_wave_counter(3000, 4, True, stream=1), True),
+                        (QI.plane_wave_cone(3000, 5, False), False),
+                        (QI.plane_wave_cone(3000, 5, True, stream=1), True),
+                        (QI.paper_uniform(3000, 6), False)):
+        d = dev_pop(pop, torch.float64)
+        sp = Q.PHOTON if photon else Q.ELECTRON
+        p = Q.particles(d, sp)
+        out = torch.empty_like(d["ux"])
+        (Q.chi_photon if photon else Q.chi_lepton)(ctx, p, out)
+        torch.cuda.synchronize()
+        ref = O.chi_array(pop, photon)
+        assert rel_close(host(out), ref, 1e-14, floor=1e-300) <= 1.0
+
+
+def test_init_optical_depth_matches_oracle(ctx):
+    pop = QI.plane_wave_counter(5000, 7, False)
+    d = dev_pop(pop, torch.float64)
+    p = Q.particles(d, Q.POSITRON, id_base=123456789)
+    Q.init_optical_depth(ctx, p, seed=99)
+    op = O.Particles(pop, O.POSITRON, id_base=123456789)
+    O.init_optical_depth(op, 99)
+    torch.cuda.synchronize()
+    assert rel_close(host(d["tau"]), op["tau"], 1e-15) <= 1.0
+
+
+def test_evolve_matches_oracle(ctx, tabs):
+    (bw, qs), (obw, oqs) = tabs
+    for photon in (False, True):
+        pop = QI.plane_wave_counter(20000, 8, photon, stream=int(photon))
+        sp = O.PHOTON if photon else O.ELECTRON
+        op = O.Particles(pop, sp)
+        O.init_optical_depth(op, 3)
+        d = dev_pop(pop, torch.float64, tau=op["tau"])
+        p = Q.particles(d, sp)
+        fl = torch.zeros(len(pop["ux"]), dtype=torch.uint8, device="cuda")
+        Q.evolve_optical_depth(ctx, bw if photon else qs, p, 1e-16, flags=fl)
+        ofl = np.zeros(op.n, dtype=np.uint8)
+        O.evolve(obw if photon else oqs, op, 1e-16, ofl)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(fl.cpu().numpy(), ofl)
+        assert ofl.sum() > 0
+        assert rel_close(host(d["tau"]), op["tau"], RTOL) <= 1.0
+
+
+def _run_steps(ctx, tabs, n_e, n_g, steps, seed=1, dt=1e-16, threshold=0.0, cap=None, tiles=None,
+               check_each_step=True):
+    """Run the fused step on GPU and the oracle side by side; compare."""
+    (bw, qs), (obw, oqs) = tabs
+    el, ph = QI.c1_population(seed=seed, n=max(n_e, n_g))
+    el = {k: v[:n_e] for k, v in el.items()}
+    ph = {k: v[:n_g] for k, v in ph.items()}
+    oe, og = O.Particles(el, O.ELECTRON, id_base=0), O.Particles(ph, O.PHOTON, id_base=1 << 40)
+    O.init_optical_depth(oe, seed)
+    O.init_optical_depth(og, seed)
+    de, dg = dev_pop(el, torch.float64), dev_pop(ph, torch.float64)
+    pe, pg = Q.particles(de, Q.ELECTRON, 0), Q.particles(dg, Q.PHOTON, 1 << 40)
+    Q.init_optical_depth(ctx, pe, seed)
+    Q.init_optical_depth(ctx, pg, seed)
+    torch.cuda.synchronize()
+    assert rel_close(host(de["tau"]), oe["tau"], 1e-15) <= 1.0
+    # the GPU path continues from the oracle's initial tau bit for bit
+    de["tau"].copy_(torch.as_tensor(oe["tau"]))
+    dg["tau"].copy_(torch.as_tensor(og["tau"]))
+    capacity = cap if cap is not None else steps * max(n_e, n_g, 1)
+    ph_b = Q.AppendBuffer(capacity, torch.float64)
+    el_b = Q.AppendBuffer(capacity, torch.float64)
+    po_b = Q.AppendBuffer(capacity, torch.float64)
+    o_ph, o_el, o_po = O.Append(capacity), O.Append(capacity), O.Append(capacity)
+    fe = torch.zeros(max(n_e, 1), dtype=torch.uint8, device="cuda")
+    fg = torch.zeros(max(n_g, 1), dtype=torch.uint8, device="cuda")
+    stats = torch.zeros(Q.STATS_LEN, dtype=torch.int64, device="cuda")
+    desc = Q.StepDesc([pe, pg], bw=bw, qs=qs, photons=ph_b, electrons=el_b, positrons=po_b,
+                      flags=[fe, fg], stats=stats, dt=dt, seed=seed, photon_min_energy=threshold, tiles=tiles)
+    total_events = 0
+    for s in range(steps):
+        desc.set_step(s)
+        Q.step(ctx, desc)
+        ofe = np.zeros(max(n_e, 1), dtype=np.uint8)
+        ofg = np.zeros(max(n_g, 1), dtype=np.uint8)
+        if tiles is None:
+            total_events += O.step(obw, oqs, oe, dt, seed, s, o_ph, photon_min_energy=threshold, flags=ofe[:n_e])
+            total_events += O.step(obw, oqs, og, dt, seed, s, o_el, o_po, flags=ofg[:n_g])
+        else:
+            total_events += _oracle_tiles(obw, oqs, [oe, og], tiles, dt, seed, s, o_ph, o_el, o_po, threshold,
+                                          [ofe, ofg])
+        torch.cuda.synchronize()
+        if check_each_step or s == steps - 1:
+            if n_e:
+                np.testing.assert_array_equal(fe[:n_e].cpu().numpy(), ofe[:n_e], err_msg=f"electron flags step {s}")
+            if n_g:
+                np.testing.assert_array_equal(fg[:n_g].cpu().numpy(), ofg[:n_g], err_msg=f"photon flags step {s}")
+            for d, o in ((de, oe), (dg, og)):
+                if o.n == 0:
+                    continue
+                umag = np.sqrt(o["ux"] ** 2 + o["uy"] ** 2 + o["uz"] ** 2)
+                assert rel_close(host(d["tau"]), o["tau"], RTOL) <= 1.0, f"tau step {s}"
+                for k in ("ux", "uy", "uz"):
+                    assert rel_close(host(d[k]), o[k], RTOL, floor=np.maximum(umag, 1e-300)) <= 1.0
+            compare_append(ph_b, o_ph, RTOL, f"photons step {s}")
+            compare_append(el_b, o_el, RTOL, f"electrons step {s}")
+            compare_append(po_b, o_po, RTOL, f"positrons step {s}")
+    st = stats.cpu().numpy()
+    assert st[Q.STAT_SCAN_TIMEOUT] == 0
+    assert st[Q.STAT_UPDATES] == steps * (n_e + n_g)
+    assert st[Q.STAT_QS_EVENTS] + st[Q.STAT_BW_EVENTS] == total_events
+    return total_events, (ph_b, el_b, po_b), (o_ph, o_el, o_po)
+
+
+def _oracle_tiles(obw, oqs, osets, tiles, dt, seed, s, o_ph, o_el, o_po, threshold, oflags):
+    """Oracle over tiles: leptons' tiles first then photons' tiles, each in
+    tile order, every tile an index range of its set (ids preserved)."""
+    ev = 0
+    for stream in (0, 1):
+        for (si, b, e) in np.asarray(tiles).reshape(-1, 3):
+            o = osets[si]
+            if (o.species == O.PHOTON) != (stream == 1) or e <= b:
+                continue
+            sub = {k: o[k][b:e] for k in O.Particles.KEYS if k != "tau"}
+            t = O.Particles(sub, o.species, id_base=o.id_base + b, tau=o["tau"][b:e])
+            f = np.zeros(e - b, dtype=np.uint8)
+            if stream == 0:
+                ev += O.step(obw, oqs, t, dt, seed, s, o_ph, photon_min_energy=threshold, flags=f)
+            else:
+                ev += O.step(obw, oqs, t, dt, seed, s, o_el, o_po, flags=f)
+            for k in O.Particles.KEYS:
+                o[k][b:e] = t[k]
+            oflags[si][b:e] = f
+    return ev
+
+
+def test_c1_fused_step_ten_steps(ctx, tabs):
+    """The parity workload: 2^16 electrons + 2^16 photons, 10 steps."""
+    ev, _, _ = _run_steps(ctx, tabs, 1 << 16, 1 << 16, 10)
+    assert ev > 1000
+
+
+@pytest.mark.parametrize("n_e,n_g", [(1, 0), (0, 1), (4095, 4097), (12289, 300), (0, 0)])
+def test_ragged_and_empty(ctx, tabs, n_e, n_g):
+    _run_steps(ctx, tabs, n_e, n_g, 3, seed=3)
+
+
+def test_tiles_follow_tile_order(ctx, tabs):
+    n = 20000
+    # electrons split into 5 tiles listed out of index order, photons into 3
+    tiles = [(0, 12000, 20000), (0, 0, 5000), (1, 9000, 20000), (0, 5000, 7000), (1, 0, 9000),
+             (0, 7000, 12000)]
+    _run_steps(ctx, tabs, n, n, 2, seed=4, tiles=tiles)
+
+
+def test_photon_threshold(ctx, tabs):
+    ev, (ph_b, _, _), (o_ph, _, _) = _run_steps(ctx, tabs, 30000, 10, 3, seed=5, threshold=2.0)
+    assert 0 < o_ph.count < ev
+
+
+def test_capacity_overflow_counts_and_prefix(ctx, tabs):
+    ev, (ph_b, el_b, po_b), (o_ph, _, _) = _run_steps(ctx, tabs, 20000, 20000, 2, seed=6, cap=50)
+    assert ph_b.read_count() == o_ph.count > ph_b.capacity == 50
+
+
+def test_bit_identical_rerun(ctx, tabs):
+    (bw, qs), _ = tabs
+    el, ph = QI.c1_population(seed=9, n=30000)
+    outs = []
+    for _ in range(2):
+        de, dg = dev_pop(el, torch.float64), dev_pop(ph, torch.float64)
+        pe, pg = Q.particles(de, Q.ELECTRON, 0), Q.particles(dg, Q.PHOTON, 1 << 40)
+        Q.init_optical_depth(ctx, pe, 9)
+        Q.init_optical_depth(ctx, pg, 9)
+        bufs = [Q.AppendBuffer(200000, torch.float64) for _ in range(3)]
+        desc = Q.StepDesc([pe, pg], bw=bw, qs=qs, photons=bufs[0], electrons=bufs[1], positrons=bufs[2],
+                          dt=1e-16, seed=9)
+        for s in range(4):
+            desc.set_step(s)
+            Q.step(ctx, desc)
+        torch.cuda.synchronize()
+        outs.append([t.cpu().numpy().copy() for t in list(de.values()) + list(dg.values())] +
+                    [b.a[k].cpu().numpy().copy() for b in bufs for k in b.a] + [b.parent.cpu().numpy() for b in bufs])
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_standalone_generate_matches_oracle(ctx, tabs):
+    (bw, qs), (obw, oqs) = tabs
+    n = 9000
+    for photon in (False, True):
+        pop = QI.plane_wave_counter(n, 10, photon, stream=int(photon))
+        sp = O.PHOTON if photon else O.ELECTRON
+        flags = (np.arange(n) % 3 == 0).astype(np.uint8)
+        op = O.Particles(pop, sp, id_base=777)
+        O.init_optical_depth(op, 10)
+        d = dev_pop(pop, torch.float64, tau=op["tau"])
+        p = Q.particles(d, sp, 777)
+        fl = torch.as_tensor(flags).cuda()
+        a1, a2 = Q.AppendBuffer(n, torch.float64), Q.AppendBuffer(n, torch.float64)
+        o1, o2 = O.Append(n), O.Append(n)
+        if photon:
+            Q.generate_pairs(ctx, bw, p, fl, 10, 42, a1, a2)
+            O.generate(obw, oqs, op, flags, 10, 42, o1, o2)
+        else:
+            Q.generate_photon_and_update_momentum(ctx, qs, p, fl, 10, 42, a1)
+            O.generate(obw, oqs, op, flags, 10, 42, o1)
+        torch.cuda.synchronize()
+        compare_append(a1, o1, RTOL, "generate a1")
+        if photon:
+            compare_append(a2, o2, RTOL, "generate a2")
+        assert rel_close(host(d["tau"]), op["tau"], RTOL) <= 1.0
+        for k in ("ux", "uy", "uz"):
+            assert rel_close(host(d[k]), op[k], RTOL, floor=1.0) <= 1.0

@@ -1,0 +1,102 @@
+"""Library checks that need no GPU: the C ABI loads and exports every
+declared symbol, host-side table generation agrees with the oracle's
+independent quadrature, table files round-trip and reject corruption, and
+invalid arguments are refused before anything is launched."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2110_00256_amd as Q
+from oracle import oracle as O
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "qedmi.h")
+
+
+def test_every_declared_symbol_is_exported():
+    src = open(HEADER).read()
+    declared = set(re.findall(r"^\s*(?:int32_t|void|const char\*)\s+(qed_\w+)\s*\(", src, re.M))
+    assert declared == set(Q.EXPORTS)
+    L = Q.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert "gfx950" in Q.version()
+
+
+@pytest.mark.parametrize("proc,cmin,cmax,nc,nf", [
+    (Q.BW, 1e-3, 1e2, 64, 64),
+    (Q.QS, 1e-3, 1e2, 64, 64),
+    (Q.BW, 1e-4, 1e3, 12, 256),
+    (Q.QS, 1e-4, 1e3, 12, 256),
+])
+def test_library_tables_match_oracle(proc, cmin, cmax, nc, nf):
+    t = Q.Table.generate(proc, cmin, cmax, nc, nf)
+    p, lr, cdf = t.host_data()
+    assert (p.n_chi, p.n_frac) == (nc, nf)
+    ot = O.Table(proc, cmin, cmax, nc, nf)
+    assert np.max(np.abs(lr - ot.ln_rate) / np.maximum(1, np.abs(ot.ln_rate))) < 1e-13
+    if proc == Q.BW:
+        assert np.all(cdf[:, 0] == 0) and np.all(cdf[:, -1] == 0.5)
+        assert np.max(np.abs(cdf - ot.cdf) / np.maximum(ot.cdf, 1e-10)) < 1e-12
+    else:
+        assert np.all(cdf[:, -1] == 0)
+        assert np.max(np.abs(cdf - ot.cdf)) < 1e-13
+
+
+def test_table_file_roundtrip_and_corruption(tmp_path):
+    t = Q.Table.generate(Q.QS, 1e-2, 1e1, 8, 16)
+    path = str(tmp_path / "qs.tab")
+    t.save(path)
+    u = Q.Table.load(path)
+    p0, lr0, c0 = t.host_data()
+    p1, lr1, c1 = u.host_data()
+    np.testing.assert_array_equal(lr0, lr1)
+    np.testing.assert_array_equal(c0, c1)
+    raw = bytearray(open(path, "rb").read())
+    raw[200] ^= 0x40
+    bad = str(tmp_path / "bad.tab")
+    open(bad, "wb").write(bytes(raw))
+    with pytest.raises(Q.QedError) as e:
+        Q.Table.load(bad)
+    assert e.value.code == Q.QED_ERR_IO
+    open(bad, "wb").write(bytes(raw[:100]))
+    with pytest.raises(Q.QedError) as e:
+        Q.Table.load(bad)
+    assert e.value.code == Q.QED_ERR_IO
+    with pytest.raises(Q.QedError) as e:
+        Q.Table.load(str(tmp_path / "missing.tab"))
+    assert e.value.code == Q.QED_ERR_IO
+
+
+def test_from_host_wraps_arrays():
+    ot = O.Table(O.BW, 1e-2, 1e1, 6, 9)
+    t = Q.Table.from_host(Q.BW, 1e-2, 1e1, ot.ln_rate, ot.cdf)
+    _, lr, cdf = t.host_data()
+    np.testing.assert_array_equal(lr, ot.ln_rate)
+    np.testing.assert_array_equal(cdf, ot.cdf)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(process=7), dict(n_chi=1), dict(n_frac=2), dict(chi_min=0.0), dict(chi_max=1e-5),
+    dict(process=Q.QS, frac_min=1.5),
+])
+def test_invalid_table_params(kw):
+    args = dict(process=Q.BW, chi_min=1e-3, chi_max=1e2, n_chi=8, n_frac=8, frac_min=1e-12)
+    args.update(kw)
+    p = Q.TableParams(args["process"], args["n_chi"], args["n_frac"], 1, args["chi_min"], args["chi_max"],
+                      args["frac_min"])
+    h = C.c_void_p()
+    assert Q.lib().qed_table_generate(C.byref(p), C.byref(h)) == Q.QED_ERR_INVALID
+    assert h.value is None
+    assert Q.lib().qed_last_error()
+
+
+def test_null_arguments_are_refused_without_launch():
+    L = Q.lib()
+    assert L.qed_step(None, None, None) == Q.QED_ERR_INVALID
+    assert L.qed_chi_lepton(None, None, 0, None, None) == Q.QED_ERR_INVALID
+    assert L.qed_read_count(None, None, None) == Q.QED_ERR_INVALID
+    assert L.qed_table_to_device(None, None) == Q.QED_ERR_INVALID
+    assert L.qed_context_create(0, None) == Q.QED_ERR_INVALID
