@@ -191,6 +191,19 @@ int32_t qed_generate_photon_and_update_momentum(qed_context* ctx, const qed_tabl
                                                 double photon_min_energy, qed_append* photons,
                                                 void* stream);
 
+/* Total rate dN/dt in 1/s for n (chi, gamma) pairs (device arrays of
+ * `dtype`): BW tables give (alpha m c^2/hbar)(chi/gamma) T(chi) (Sec. 2.1),
+ * QS tables (2/3)(alpha m c^2/hbar) G(chi)/gamma (Sec. 2.2), with the
+ * table interpolation and out-of-table rules of the step. */
+int32_t qed_table_rate(const qed_table* t, int32_t dtype, const void* chi, const void* gamma, void* rate_out,
+                       int64_t n, void* stream);
+
+/* Inverse-CDF sample for n (chi, u) pairs, u in (0, 1) (Sec. 3.1 / 3.2
+ * sampling).  BW: out = xi in [0, 1/2], electron_selected[i] = (u <= 1/2)
+ * (may be NULL).  QS: out = ln xi.  Device arrays of `dtype`. */
+int32_t qed_table_sample(const qed_table* t, int32_t dtype, const void* chi, const void* u, void* out,
+                         uint8_t* electron_selected, int64_t n, void* stream);
+
 /* ------------------------------------------------------------- fused step
  * One QED sub-step over several species in a single persistent launch:
  * chi, rate, tau update, event test, and for events the draws, sampling,

@@ -31,6 +31,7 @@ EXPORTS = (
     "qed_context_create", "qed_context_destroy",
     "qed_chi_lepton", "qed_chi_photon", "qed_init_optical_depth", "qed_evolve_optical_depth",
     "qed_generate_pairs", "qed_generate_photon_and_update_momentum", "qed_step", "qed_read_count",
+    "qed_table_rate", "qed_table_sample",
     "qed_surrogate_train", "qed_surrogate_from_host", "qed_surrogate_get_params",
     "qed_surrogate_forward", "qed_surrogate_grad", "qed_surrogate_sample", "qed_surrogate_destroy",
     "qed_last_error", "qed_version",
@@ -105,6 +106,8 @@ def lib():
                                                         P(AppendC), vp],
             "qed_step": [vp, P(StepDescC), vp],
             "qed_read_count": [P(AppendC), P(i64), vp],
+            "qed_table_rate": [vp, i32, vp, vp, vp, i64, vp],
+            "qed_table_sample": [vp, i32, vp, vp, vp, vp, i64, vp],
             "qed_surrogate_train": [vp, vp, P(SurrogateCfg), P(vp), P(C.c_float), vp],
             "qed_surrogate_from_host": [vp, P(SurrogateCfg), vp, P(vp)],
             "qed_surrogate_get_params": [vp, vp],
@@ -206,6 +209,16 @@ class Context:
         if getattr(self, "h", None) is not None and self.h.value and _lib is not None:
             _lib.qed_context_destroy(self.h)
             self.h = None
+
+
+def table_rate(table: Table, chi, gamma, out, stream=None):
+    check(lib().qed_table_rate(table.h, dtype_code(chi), _ptr(chi), _ptr(gamma), _ptr(out), chi.numel(),
+                               _stream(stream)))
+
+
+def table_sample(table: Table, chi, u, out, electron_selected=None, stream=None):
+    check(lib().qed_table_sample(table.h, dtype_code(chi), _ptr(chi), _ptr(u), _ptr(out), _ptr(electron_selected),
+                                 chi.numel(), _stream(stream)))
 
 
 # --------------------------------------------------------------- particles

@@ -412,6 +412,37 @@ extern "C" int32_t qed_generate_photon_and_update_momentum(qed_context* ctx, con
     return run_chunks(ctx, &d, true, static_cast<hipStream_t>(stream));
 }
 
+static int32_t table_call(const qed_table* t, int32_t dtype, const void* a, const void* b, void* out, uint8_t* sel,
+                          int64_t n, void* stream, bool sample) {
+    if (!t) { set_error("table is null"); return QED_ERR_INVALID; }
+    if (t->device < 0 || !t->d_ln_rate64) { set_error("table is not on the device"); return QED_ERR_STATE; }
+    if (dtype != QED_FP64 && dtype != QED_FP32) { set_error("dtype must be FP64 or FP32"); return QED_ERR_INVALID; }
+    if (n < 0) { set_error("n < 0"); return QED_ERR_INVALID; }
+    if (n == 0) return QED_OK;
+    if (!a || !b || !out) { set_error("null array"); return QED_ERR_INVALID; }
+    TableCallArgs c{};
+    c.table = t->view();
+    c.a = a;
+    c.b = b;
+    c.out = out;
+    c.sel = sel;
+    c.n = n;
+    c.process = t->p.process;
+    const hipError_t e = sample ? launch_table_sample(c, dtype, static_cast<hipStream_t>(stream))
+                                : launch_table_rate(c, dtype, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? QED_OK : hip_fail(e, "table kernel launch");
+}
+
+extern "C" int32_t qed_table_rate(const qed_table* t, int32_t dtype, const void* chi, const void* gamma,
+                                  void* rate_out, int64_t n, void* stream) {
+    return table_call(t, dtype, chi, gamma, rate_out, nullptr, n, stream, false);
+}
+
+extern "C" int32_t qed_table_sample(const qed_table* t, int32_t dtype, const void* chi, const void* u, void* out,
+                                    uint8_t* electron_selected, int64_t n, void* stream) {
+    return table_call(t, dtype, chi, u, out, electron_selected, n, stream, true);
+}
+
 extern "C" int32_t qed_read_count(const qed_append* a, int64_t* host_count, void* stream) {
     if (!a || !a->count || !host_count) { set_error("append/count/host_count is null"); return QED_ERR_INVALID; }
     hipStream_t s = static_cast<hipStream_t>(stream);

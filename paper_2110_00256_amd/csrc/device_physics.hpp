@@ -131,31 +131,38 @@ __device__ __forceinline__ ChiGamma chi_f32(float ux, float uy, float uz, float 
 
 // ------------------------------------------------------ compensated FP32
 // Double-float arithmetic (value = hi + lo, |lo| <= ulp(hi)/2) built from
-// the error-free transformations TwoSum (Knuth) and TwoProd (fma).
+// the error-free transformations TwoSum (Knuth) and TwoProd (fma).  These
+// need every product and sum rounded as written, so contraction into fused
+// multiply-adds is switched off inside them.
 struct DF {
     float hi, lo;
 };
 __device__ __forceinline__ DF df_two_sum(float a, float b) {
+#pragma clang fp contract(off)
     const float s = a + b;
     const float bb = s - a;
     return {s, (a - (s - bb)) + (b - bb)};
 }
 __device__ __forceinline__ DF df_fast_sum(float a, float b) {
+#pragma clang fp contract(off)
     const float s = a + b;
     return {s, b - (s - a)};
 }
 __device__ __forceinline__ DF df_add(DF x, DF y) {
+#pragma clang fp contract(off)
     DF s = df_two_sum(x.hi, y.hi);
     return df_fast_sum(s.hi, s.lo + x.lo + y.lo);
 }
 __device__ __forceinline__ DF df_neg(DF x) { return {-x.hi, -x.lo}; }
 __device__ __forceinline__ DF df_mul(DF x, DF y) {
+#pragma clang fp contract(off)
     const float p = x.hi * y.hi;
     const float e = fmaf(x.hi, y.hi, -p);
     return df_fast_sum(p, e + (x.hi * y.lo + x.lo * y.hi));
 }
 __device__ __forceinline__ DF df_from(float a) { return {a, 0.0f}; }
 __device__ __forceinline__ DF df_sqrt(DF x) {
+#pragma clang fp contract(off)
     if (!(x.hi > 0.0f)) return {0.0f, 0.0f};
     const float s = sqrtf(x.hi);
     const float p = s * s;
@@ -164,6 +171,7 @@ __device__ __forceinline__ DF df_sqrt(DF x) {
     return df_fast_sum(s, r);
 }
 __device__ __forceinline__ DF df_div(DF x, DF y) {
+#pragma clang fp contract(off)
     const float q1 = x.hi / y.hi;
     const DF r = df_add(x, df_neg(df_mul(df_from(q1), y)));
     const float q2 = r.hi / y.hi;

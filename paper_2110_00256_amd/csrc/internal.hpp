@@ -101,6 +101,18 @@ hipError_t launch_init_tau(const ElemArgs& a, int dtype, hipStream_t s);
 hipError_t launch_evolve(const ElemArgs& a, int dtype, hipStream_t s);
 int step_grid_size(int dtype, int device);
 
+struct TableCallArgs {
+    TableDev table;
+    const void* a;        // chi
+    const void* b;        // gamma (rate) or u (sample)
+    void* out;
+    uint8_t* sel;
+    int64_t n;
+    int32_t process;
+};
+hipError_t launch_table_rate(const TableCallArgs& a, int dtype, hipStream_t s);
+hipError_t launch_table_sample(const TableCallArgs& a, int dtype, hipStream_t s);
+
 }  // namespace qedmi
 
 struct qed_table {

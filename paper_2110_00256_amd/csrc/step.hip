@@ -62,28 +62,33 @@ __device__ __forceinline__ unsigned bits_below(unsigned long long mask) {
 
 // Decoupled look-back for chunk k with aggregate agg; returns the exclusive
 // prefix over earlier chunks of its stream.  Called by one thread.
+// A status word carries the launch epoch, the flag and the value together,
+// so relaxed device-scope atomics are enough: no other data is published
+// through it.  (Acquire/release at device scope would invalidate or write
+// back the whole L2 of the XCD on every poll.)  The base counts read before
+// phase 1 complete before the aggregate is published: their values are
+// stored to LDS first.
 __device__ long long look_back(const StepArgs& a, int k, const ChunkDesc& c, unsigned long long agg,
                                int64_t* err) {
     unsigned long long* st_k = a.status + k;
     if (k == c.stream_first) {
-        __hip_atomic_store(st_k, pack_status(a.epoch, kFlagP, agg), __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(st_k, pack_status(a.epoch, kFlagP, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return 0;
     }
-    __hip_atomic_store(st_k, pack_status(a.epoch, kFlagA, agg), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(st_k, pack_status(a.epoch, kFlagA, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     long long excl = 0;
     int j = k - 1;
     int spins = 0;
     while (j >= c.stream_first) {
         const unsigned long long v =
-            __hip_atomic_load(a.status + j, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_load(a.status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned flag = static_cast<unsigned>(v >> 30) & 3u;
         if (static_cast<uint32_t>(v >> 32) != a.epoch || flag == 0u) {
             if (++spins > kSpinLimit) {   // predecessor never published: give up, report
                 if (err) atomicAdd(reinterpret_cast<unsigned long long*>(err), 1ULL);
                 break;
             }
-            __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_s_sleep(1);
             continue;
         }
         excl += static_cast<long long>(v & kValueMask);
@@ -91,7 +96,7 @@ __device__ long long look_back(const StepArgs& a, int k, const ChunkDesc& c, uns
         --j;
     }
     __hip_atomic_store(st_k, pack_status(a.epoch, kFlagP, static_cast<unsigned long long>(excl) + agg),
-                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return excl;
 }
 
@@ -401,6 +406,30 @@ __global__ void __launch_bounds__(256) evolve_kernel(ElemArgs a) {
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) table_rate_kernel(TableCallArgs a) {
+    const T* lr = ln_rate_ptr<T>(a.table);
+    for (int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; j < a.n; j += int64_t(gridDim.x) * blockDim.x) {
+        const T chi = ld<T>(a.a, j), g = ld<T>(a.b, j);
+        st<T>(a.out, j, a.process == QED_PROC_BW ? dev::rate_bw<T>(lr, a.table, chi, g)
+                                                 : dev::rate_qs<T>(lr, a.table, chi, g));
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) table_sample_kernel(TableCallArgs a) {
+    for (int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; j < a.n; j += int64_t(gridDim.x) * blockDim.x) {
+        const T chi = ld<T>(a.a, j), r = ld<T>(a.b, j);
+        if (a.process == QED_PROC_BW) {
+            bool e;
+            st<T>(a.out, j, dev::sample_bw<T>(a.table, chi, r, e));
+            if (a.sel) a.sel[j] = static_cast<uint8_t>(e);
+        } else {
+            st<T>(a.out, j, dev::sample_qs_lnxi<T>(a.table, chi, r));
+        }
+    }
+}
+
 size_t step_lds_bytes(const StepArgs& a, size_t elem) {
     const int nbw = a.bw.n_chi > 0 ? a.bw.n_chi : 0;
     const int nqs = a.qs.n_chi > 0 ? a.qs.n_chi : 0;
@@ -444,6 +473,20 @@ int step_grid_size(int dtype, int device) {
                                                          sizeof(float) * 2 * kMaxTableChi + 2 * kChunk);
     if (e != hipSuccess || per_cu <= 0) per_cu = 4;
     return cus * per_cu;
+}
+
+hipError_t launch_table_rate(const TableCallArgs& a, int dtype, hipStream_t s) {
+    const int g = elem_grid(a.n);
+    if (dtype == QED_FP64) hipLaunchKernelGGL((table_rate_kernel<double>), dim3(g), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((table_rate_kernel<float>), dim3(g), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_sample(const TableCallArgs& a, int dtype, hipStream_t s) {
+    const int g = elem_grid(a.n);
+    if (dtype == QED_FP64) hipLaunchKernelGGL((table_sample_kernel<double>), dim3(g), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((table_sample_kernel<float>), dim3(g), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_chi(const ElemArgs& a, int dtype, hipStream_t s) {
