@@ -95,6 +95,8 @@ def lib():
         L.orc_chi_n.argtypes = [C.c_int64] + [_dp] * 9 + [i, _dp]
         L.orc_rate_n.argtypes = [C.POINTER(_Table), C.c_int64, _dp, _dp, _dp]
         L.orc_sample_n.argtypes = [C.POINTER(_Table), C.c_int64, _dp, _dp, _dp, _u8p]
+        L.orc_mlp_grad.argtypes = [_dp, C.c_int64, _dp, _dp, _dp, _dp, _dp, i]
+        L.orc_mlp_grad.restype = d
         _lib = L
     return _lib
 
@@ -330,3 +332,26 @@ def generate(bw: Table, qs: Table, p: Particles, flags: np.ndarray, seed: int, s
 def evolve(t: Table, p: Particles, dt: float, flags=None):
     fl = None if flags is None else _ptr(flags, _u8p)
     lib().orc_evolve(t.cstruct, p.cstruct, dt, fl)
+
+
+# ---------------------------------------------------------------- MLP
+MLP_NPARAM = 4417
+
+
+def mlp_forward(params, x, bf16=False):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 2)
+    y = np.zeros(len(x))
+    lib().orc_mlp_grad(_ptr(p), len(x), _ptr(x), None, None, None, _ptr(y), int(bf16))
+    return y
+
+
+def mlp_grad(params, x, t, w=None, bf16=False):
+    """(loss, grad) of 0.5 sum w (y - t)^2 / n."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 2)
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    g = np.zeros(MLP_NPARAM)
+    wp = None if w is None else _ptr(np.ascontiguousarray(w, dtype=np.float64))
+    loss = lib().orc_mlp_grad(_ptr(p), len(x), _ptr(x), _ptr(t), wp, _ptr(g), None, int(bf16))
+    return loss, g

@@ -785,3 +785,78 @@ void orc_sample_n(const orc_table* t, int64_t n, const double* chi, const double
         }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* MLP reference for the learned inverse-CDF surrogate (not in the paper:   */
+/* the library's learned replacement of the Sec. 3.1 / 3.2 table lookup).   */
+/* 2 -> 64 -> 64 -> 1, SiLU, loss 0.5 sum_i w_i (y_i - t_i)^2 / n.          */
+/* Parameter layout: W1[64][2], b1[64], W2[64][64] (row = output unit),     */
+/* b2[64], W3[64], b3.  FP64 throughout; with `bf16` set, the operands the  */
+/* library feeds to its BF16 matrix instructions (W2 and h1 forward; dz2    */
+/* and h1 for dW2; dz2 and W2 for dh1) are rounded to bfloat16 first.       */
+/* ------------------------------------------------------------------------ */
+static double orc_bf16(double v) {
+    float f = (float)v;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    u &= 0xffff0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+static double orc_silu(double z) { return z / (1.0 + exp(-z)); }
+static double orc_dsilu(double z) {
+    double s = 1.0 / (1.0 + exp(-z));
+    return s * (1.0 + z * (1.0 - s));
+}
+
+#define H 64
+double orc_mlp_grad(const double* p, int64_t n, const double* x, const double* t, const double* w, double* grad,
+                    double* y_out, int bf16) {
+    const double *W1 = p, *b1 = p + 128, *W2 = p + 192, *b2 = p + 192 + 4096, *W3 = p + 192 + 4096 + 64;
+    double b3 = p[192 + 4096 + 128];
+    if (grad) memset(grad, 0, sizeof(double) * 4417);
+    double loss = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double z1[H], h1[H], h1q[H], z2[H], h2[H];
+        for (int k = 0; k < H; ++k) {
+            z1[k] = W1[2 * k] * x[2 * i] + W1[2 * k + 1] * x[2 * i + 1] + b1[k];
+            h1[k] = orc_silu(z1[k]);
+            h1q[k] = bf16 ? orc_bf16(h1[k]) : h1[k];
+        }
+        double y = b3;
+        for (int j = 0; j < H; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < H; ++k) s += (bf16 ? orc_bf16(W2[j * H + k]) : W2[j * H + k]) * h1q[k];
+            z2[j] = s + b2[j];
+            h2[j] = orc_silu(z2[j]);
+            y += W3[j] * h2[j];
+        }
+        if (y_out) y_out[i] = y;
+        if (!t || !grad) continue;
+        double wi = w ? w[i] : 1.0;
+        double r = y - t[i];
+        loss += 0.5 * wi * r * r / (double)n;
+        double dy = wi * r / (double)n;
+        double *gW1 = grad, *gb1 = grad + 128, *gW2 = grad + 192, *gb2 = grad + 192 + 4096, *gW3 = gb2 + 64;
+        grad[192 + 4096 + 128] += dy;
+        double dz2[H], dz2q[H];
+        for (int j = 0; j < H; ++j) {
+            gW3[j] += dy * h2[j];
+            dz2[j] = dy * W3[j] * orc_dsilu(z2[j]);
+            dz2q[j] = bf16 ? orc_bf16(dz2[j]) : dz2[j];
+            gb2[j] += dz2[j];
+            for (int k = 0; k < H; ++k) gW2[j * H + k] += dz2q[j] * h1q[k];
+        }
+        for (int k = 0; k < H; ++k) {
+            double dh = 0.0;
+            for (int j = 0; j < H; ++j) dh += dz2q[j] * (bf16 ? orc_bf16(W2[j * H + k]) : W2[j * H + k]);
+            double dz1 = dh * orc_dsilu(z1[k]);
+            gW1[2 * k] += dz1 * x[2 * i];
+            gW1[2 * k + 1] += dz1 * x[2 * i + 1];
+            gb1[k] += dz1;
+        }
+    }
+    return loss;
+}
+#undef H

@@ -340,3 +340,54 @@ def step(ctx, desc: StepDesc, stream=None):
 
 def version():
     return lib().qed_version().decode()
+
+
+# --------------------------------------------------------------- surrogate
+class Surrogate:
+    """Learned inverse CDF (qed_surrogate*)."""
+
+    def __init__(self, handle, table):
+        self.h = C.c_void_p(handle)
+        self._table = table
+
+    @staticmethod
+    def cfg(process, chi_lo, chi_hi, n_samples=1 << 22, batch=16384, steps=20000, lr=3e-3, probe_tol=0.5,
+            seed=7):
+        return SurrogateCfg(process, n_samples, batch, steps, lr, probe_tol, chi_lo, chi_hi, seed)
+
+    @classmethod
+    def train(cls, ctx, table, cfg, stream=None):
+        h = C.c_void_p()
+        loss = C.c_float()
+        check(lib().qed_surrogate_train(ctx.h, table.h, C.byref(cfg), C.byref(h), C.byref(loss), _stream(stream)))
+        return cls(h.value, table), loss.value
+
+    @classmethod
+    def from_host(cls, table, cfg, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == SURR_NPARAM
+        h = C.c_void_p()
+        check(lib().qed_surrogate_from_host(table.h, C.byref(cfg), p.ctypes.data, C.byref(h)))
+        return cls(h.value, table)
+
+    def params(self):
+        import numpy as np
+        p = np.zeros(SURR_NPARAM, dtype=np.float32)
+        check(lib().qed_surrogate_get_params(self.h, p.ctypes.data))
+        return p
+
+    def forward(self, x, y, stream=None):
+        check(lib().qed_surrogate_forward(self.h, _ptr(x), _ptr(y), y.numel(), _stream(stream)))
+
+    def grad(self, x, t, grad, loss, stream=None):
+        check(lib().qed_surrogate_grad(self.h, _ptr(x), _ptr(t), t.numel(), _ptr(grad), _ptr(loss),
+                                       _stream(stream)))
+
+    def sample(self, chi, u, out, stream=None):
+        check(lib().qed_surrogate_sample(self.h, _ptr(chi), _ptr(u), _ptr(out), chi.numel(), _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and self.h.value and _lib is not None:
+            _lib.qed_surrogate_destroy(self.h)
+            self.h = None

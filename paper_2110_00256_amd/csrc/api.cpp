@@ -185,7 +185,7 @@ int32_t launch_chunks(qed_context* ctx, StepArgs& a, int dtype, hipStream_t s) {
     int dev = 0;
     hipGetDevice(&dev);
     if (dev != ctx->device) { set_error("context belongs to another device"); return QED_ERR_INVALID; }
-    const int grid = std::max(1, std::min(a.n_chunks, step_grid_size(dtype, ctx->device)));
+    const int grid = std::max(1, std::min(a.n_chunks, step_grid_size(dtype, a.use_bw_surr || a.use_qs_surr, ctx->device)));
     ctx->epoch = ctx->epoch + 1 == 0 ? 1 : ctx->epoch + 1;
     a.status = ctx->d_status;
     a.ticket = ctx->d_ticket;
@@ -361,6 +361,10 @@ static int32_t run_chunks(qed_context* ctx, const qed_step_desc* d, bool generat
     a.step = d->step;
     a.photon_min_energy = d->photon_min_energy;
     a.chi_mode = dtype == QED_FP64 ? QED_CHI_FP64 : d->chi_mode;
+    if ((d->bw_surrogate || d->qs_surrogate) && dtype != QED_FP32) {
+        set_error("surrogate sampling runs on the FP32 path only");
+        return QED_ERR_INVALID;
+    }
     r = surrogate_bind(a, d->bw_surrogate, d->qs_surrogate);
     if (r) return r;
     return launch_chunks(ctx, a, dtype, s);

@@ -8,7 +8,8 @@
 #include <string>
 #include <vector>
 
-#include "../../include/qedmi.h"
+#include "qedmi.h"
+#include "surrogate.hpp"
 
 namespace qedmi {
 
@@ -61,8 +62,6 @@ struct ChunkDesc {
     int32_t pad_;
 };
 
-struct SurrogateDev;   // defined in surrogate.hpp
-
 struct StepArgs {
     SetDev sets[kMaxSets];
     int32_t n_sets;
@@ -76,8 +75,8 @@ struct StepArgs {
     TableDev bw, qs;
     AppendDev ph, el, po;
     int64_t* stats;
-    const SurrogateDev* bw_surr;  // device pointers, may be null
-    const SurrogateDev* qs_surr;
+    SurrogateDev bw_surr, qs_surr;  // valid when use_*_surr
+    int32_t use_bw_surr, use_qs_surr;
     double dt;
     unsigned long long seed, step;
     double photon_min_energy;
@@ -99,7 +98,7 @@ hipError_t launch_step(const StepArgs& a, int dtype, int grid, hipStream_t s);
 hipError_t launch_chi(const ElemArgs& a, int dtype, hipStream_t s);
 hipError_t launch_init_tau(const ElemArgs& a, int dtype, hipStream_t s);
 hipError_t launch_evolve(const ElemArgs& a, int dtype, hipStream_t s);
-int step_grid_size(int dtype, int device);
+int step_grid_size(int dtype, bool surr, int device);
 
 struct TableCallArgs {
     TableDev table;

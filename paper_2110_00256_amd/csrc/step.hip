@@ -112,10 +112,67 @@ __device__ __forceinline__ void write_product(const AppendDev& o, int64_t slot, 
     if (o.parent) o.parent[slot] = parent;
 }
 
-// Sampled photon fraction for a lepton event (ln xi): table or surrogate.
-template <typename T>
-__device__ __forceinline__ T qs_lnxi(const StepArgs& a, T chi, T r) {
-    return dev::sample_qs_lnxi<T>(a.qs, chi, r);
+// Surrogate sampling for the events of one wave (all 64 lanes call it
+// together; `valid` marks lanes holding an event).  Lanes outside the
+// trained domain use the table; one probe lane per wave also evaluates the
+// table and, if the network is off by more than probe_tol in its output
+// space, the whole wave falls back to the table.  Returns the network-side
+// sample (QS: ln xi; BW: xi), or NAN where the caller must use the table.
+__device__ __forceinline__ float surr_wave_sample(const StepArgs& a, const SurrogateDev& sv, const TableDev& tab,
+                                                  bool valid, float chi, float u, float* lds_y, int64_t* stats) {
+    float x0 = 0.f, x1 = 0.f;
+    const bool inside = valid && surr_inputs(sv, chi, u, x0, x1);
+    const unsigned long long in_mask = __ballot(inside);
+    if (in_mask == 0ULL) return __builtin_nanf("");
+    const float y = surr_forward_wave(sv, x0, x1, lds_y);
+    // probe: the first lane with an in-domain event
+    const unsigned probe_lane = static_cast<unsigned>(__builtin_ctzll(in_mask));
+    float err = 0.f;
+    if (__lane_id() == probe_lane) {
+        float ref;
+        if (sv.process == 1) {
+            ref = dev::sample_qs_lnxi<float>(tab, chi, u);
+        } else {
+            bool e;
+            ref = dev::sample_bw<float>(tab, chi, u, e);
+        }
+        err = fabsf(y - surr_target_of(sv.process, chi, u, ref));
+    }
+    err = __shfl(err, static_cast<int>(probe_lane));
+    const bool fallback = !(err <= sv.probe_tol);
+    if (stats && __lane_id() == probe_lane) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(stats + QED_STAT_SURR_BATCHES), 1ULL);
+        if (fallback) atomicAdd(reinterpret_cast<unsigned long long*>(stats + QED_STAT_SURR_FALLBACK), 1ULL);
+    }
+    if (fallback || !inside) return __builtin_nanf("");
+    return surr_output(sv, chi, u, y);
+}
+
+// Sampled photon fraction ln xi for a lepton event: surrogate (FP32 data)
+// or table.  Called by all lanes of the wave.
+template <typename T, bool kSurr>
+__device__ __forceinline__ T qs_lnxi(const StepArgs& a, bool valid, T chi, T r, float* lds_y) {
+    if constexpr (kSurr && sizeof(T) == 4) {
+        if (a.use_qs_surr) {
+            const float v = surr_wave_sample(a, a.qs_surr, a.qs, valid, chi, r, lds_y, a.stats);
+            if (!__builtin_isnan(v)) return v;
+        }
+    }
+    return valid ? dev::sample_qs_lnxi<T>(a.qs, chi, r) : T(0);
+}
+
+// Pair fraction xi (electron_selected out) for a photon event.
+template <typename T, bool kSurr>
+__device__ __forceinline__ T bw_xi(const StepArgs& a, bool valid, T chi, T r, bool& esel, float* lds_y) {
+    esel = r <= T(0.5);
+    if constexpr (kSurr && sizeof(T) == 4) {
+        if (a.use_bw_surr) {
+            const float v = surr_wave_sample(a, a.bw_surr, a.bw, valid, chi, r, lds_y, a.stats);
+            if (!__builtin_isnan(v)) return v;
+        }
+    }
+    bool e;
+    return valid ? dev::sample_bw<T>(a.bw, chi, r, e) : T(0);
 }
 
 // Per-event state shared by the two passes over a chunk's events.
@@ -127,14 +184,14 @@ struct EventCtx {
     dev::Draws d;
 };
 
-template <typename T, bool kPhoton>
+template <typename T, bool kPhoton, int kChiMode>
 __device__ __forceinline__ EventCtx<T> load_event(const StepArgs& a, const SetDev& S, int64_t j) {
     EventCtx<T> e;
     e.j = j;
     e.ux = ld<T>(S.p[0], j);
     e.uy = ld<T>(S.p[1], j);
     e.uz = ld<T>(S.p[2], j);
-    const dev::ChiGamma cg = dev::chi_of<T, kPhoton>(a.chi_mode, e.ux, e.uy, e.uz, ld<T>(S.p[3], j),
+    const dev::ChiGamma cg = dev::chi_of<T, kPhoton>(kChiMode, e.ux, e.uy, e.uz, ld<T>(S.p[3], j),
                                                      ld<T>(S.p[4], j), ld<T>(S.p[5], j), ld<T>(S.p[6], j),
                                                      ld<T>(S.p[7], j), ld<T>(S.p[8], j));
     e.chi = cg.chi;
@@ -146,15 +203,16 @@ __device__ __forceinline__ EventCtx<T> load_event(const StepArgs& a, const SetDe
 }
 
 // QS photon energy gamma_gamma = (gamma - 1) xi, with gamma - 1 = |u|^2/(gamma + 1).
-template <typename T>
-__device__ __forceinline__ T qs_photon_energy(const StepArgs& a, const EventCtx<T>& e, T& xi_out) {
-    const T lnxi = qs_lnxi<T>(a, static_cast<T>(e.chi), static_cast<T>(e.d.u[0]));
+template <typename T, bool kSurr>
+__device__ __forceinline__ T qs_photon_energy(const StepArgs& a, bool valid, const EventCtx<T>& e, T& xi_out,
+                                              float* lds_y) {
+    const T lnxi = qs_lnxi<T, kSurr>(a, valid, static_cast<T>(e.chi), static_cast<T>(e.d.u[0]), lds_y);
     const T xi = dev::dexp(lnxi);
     xi_out = xi;
     return static_cast<T>(e.u2 / (e.gamma + 1.0)) * xi;
 }
 
-template <typename T, int kChiMode>
+template <typename T, int kChiMode, bool kSurr>
 __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int nbw = a.bw.n_chi > 0 ? a.bw.n_chi : 0;
@@ -168,6 +226,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
     __shared__ int kpref[kChunk / 64];
     __shared__ int s_ticket, s_total, s_kept;
     __shared__ long long s_excl, s_base0, s_base1;
+    __shared__ float s_surr_y[kBlock / 64][64];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
@@ -255,12 +314,12 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
         if (thresh) {
             for (int e0 = 0; e0 < total; e0 += kBlock) {
                 const int e = e0 + tid;
-                bool keep = false;
-                if (e < total) {
-                    const EventCtx<T> ec = load_event<T, false>(a, S, c.begin + evlist[e]);
-                    T xi;
-                    keep = qs_photon_energy<T>(a, ec, xi) >= static_cast<T>(a.photon_min_energy);
-                }
+                const bool valid = e < total;
+                // idle lanes read a valid particle (the chunk's first) and discard it
+                const EventCtx<T> ec = load_event<T, false, kChiMode>(a, S, c.begin + (valid ? evlist[e] : 0));
+                T xi;
+                const T gg = qs_photon_energy<T, kSurr>(a, valid, ec, xi, s_surr_y[wave]);
+                const bool keep = valid && gg >= static_cast<T>(a.photon_min_energy);
                 const unsigned long long m = __ballot(keep);
                 if (lane == 0) kmask[(e0 >> 6) + wave] = m;
             }
@@ -311,14 +370,15 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
         // ---------------- phase 2: events
         for (int e0 = 0; e0 < total; e0 += kBlock) {
             const int e = e0 + tid;
-            if (e < total) {
-                const int64_t j = c.begin + evlist[e];
-                const int64_t parent = S.id_base + j;
-                const T w = S.p[10] ? ld<T>(S.p[10], j) : T(1);
-                if (photon) {
-                    const EventCtx<T> ec = load_event<T, true>(a, S, j);
-                    bool esel;
-                    const T xi = dev::sample_bw<T>(a.bw, static_cast<T>(ec.chi), static_cast<T>(ec.d.u[0]), esel);
+            const bool valid = e < total;
+            const int64_t j = valid ? c.begin + evlist[e] : c.begin;
+            const int64_t parent = S.id_base + j;
+            if (photon) {
+                const EventCtx<T> ec = load_event<T, true, kChiMode>(a, S, j);
+                bool esel;
+                const T xi = bw_xi<T, kSurr>(a, valid, static_cast<T>(ec.chi), static_cast<T>(ec.d.u[0]), esel, s_surr_y[wave]);
+                if (valid) {
+                    const T w = S.p[10] ? ld<T>(S.p[10], j) : T(1);
                     const T sx = xi * ec.ux, sy = xi * ec.uy, sz = xi * ec.uz;
                     const T ox = ec.ux - sx, oy = ec.uy - sy, oz = ec.uz - sz;
                     const T te = static_cast<T>(-log(ec.d.u[1]));
@@ -332,13 +392,16 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
                         write_product<T>(a.po, s_base1 + slot, sx, sy, sz, w, tp, parent);
                     }
                     st<T>(S.p[9], j, static_cast<T>(__builtin_inf()));
-                } else {
-                    const EventCtx<T> ec = load_event<T, false>(a, S, j);
-                    T xi;
-                    const T gg = qs_photon_energy<T>(a, ec, xi);
+                }
+            } else {
+                const EventCtx<T> ec = load_event<T, false, kChiMode>(a, S, j);
+                T xi;
+                const T gg = qs_photon_energy<T, kSurr>(a, valid, ec, xi, s_surr_y[wave]);
+                if (valid) {
+                    const T w = S.p[10] ? ld<T>(S.p[10], j) : T(1);
                     const T um = static_cast<T>(sqrt(ec.u2));
-                    const T s = um > T(0) ? gg / um : T(0);
-                    const T px = s * ec.ux, py = s * ec.uy, pz = s * ec.uz;
+                    const T sc = um > T(0) ? gg / um : T(0);
+                    const T px = sc * ec.ux, py = sc * ec.uy, pz = sc * ec.uz;
                     st<T>(S.p[0], j, ec.ux - px);
                     st<T>(S.p[1], j, ec.uy - py);
                     st<T>(S.p[2], j, ec.uz - pz);
@@ -436,15 +499,15 @@ size_t step_lds_bytes(const StepArgs& a, size_t elem) {
     return elem * (((nbw + 1) & ~1) + ((nqs + 1) & ~1)) + sizeof(uint16_t) * kChunk;
 }
 
-template <typename T>
+template <typename T, bool kSurr>
 hipError_t launch_step_t(const StepArgs& a, int grid, hipStream_t s) {
     const size_t lds = step_lds_bytes(a, sizeof(T));
     if (a.chi_mode == QED_CHI_COMP32)
-        hipLaunchKernelGGL((step_kernel<T, QED_CHI_COMP32>), dim3(grid), dim3(kBlock), lds, s, a);
+        hipLaunchKernelGGL((step_kernel<T, QED_CHI_COMP32, kSurr>), dim3(grid), dim3(kBlock), lds, s, a);
     else if (a.chi_mode == QED_CHI_FP32)
-        hipLaunchKernelGGL((step_kernel<T, QED_CHI_FP32>), dim3(grid), dim3(kBlock), lds, s, a);
+        hipLaunchKernelGGL((step_kernel<T, QED_CHI_FP32, kSurr>), dim3(grid), dim3(kBlock), lds, s, a);
     else
-        hipLaunchKernelGGL((step_kernel<T, QED_CHI_FP64>), dim3(grid), dim3(kBlock), lds, s, a);
+        hipLaunchKernelGGL((step_kernel<T, QED_CHI_FP64, kSurr>), dim3(grid), dim3(kBlock), lds, s, a);
     return hipGetLastError();
 }
 
@@ -456,20 +519,25 @@ int elem_grid(int64_t n) {
 }  // namespace
 
 hipError_t launch_step(const StepArgs& a, int dtype, int grid, hipStream_t s) {
-    return dtype == QED_FP64 ? launch_step_t<double>(a, grid, s) : launch_step_t<float>(a, grid, s);
+    if (dtype == QED_FP64) return launch_step_t<double, false>(a, grid, s);
+    if (a.use_bw_surr || a.use_qs_surr) return launch_step_t<float, true>(a, grid, s);
+    return launch_step_t<float, false>(a, grid, s);
 }
 
-int step_grid_size(int dtype, int device) {
+int step_grid_size(int dtype, bool surr, int device) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
         cus = 256;
     int per_cu = 0;
     hipError_t e;
     if (dtype == QED_FP64)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_kernel<double, QED_CHI_FP64>, kBlock,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_kernel<double, QED_CHI_FP64, false>, kBlock,
                                                          sizeof(double) * 2 * kMaxTableChi + 2 * kChunk);
+    else if (surr)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_kernel<float, QED_CHI_FP64, true>, kBlock,
+                                                         sizeof(float) * 2 * kMaxTableChi + 2 * kChunk);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_kernel<float, QED_CHI_FP64>, kBlock,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_kernel<float, QED_CHI_FP64, false>, kBlock,
                                                          sizeof(float) * 2 * kMaxTableChi + 2 * kChunk);
     if (e != hipSuccess || per_cu <= 0) per_cu = 4;
     return cus * per_cu;

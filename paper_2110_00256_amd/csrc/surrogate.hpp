@@ -1,5 +1,22 @@
-// Learned inverse-CDF surrogate: device-side description (weights in BF16,
-// FP32 biases) shared by the step kernel and the surrogate kernels.
+// Learned inverse-CDF surrogate: an MLP 2 -> 64 -> 64 -> 1 with SiLU
+// activations.  The 64 x 64 hidden layer runs on BF16 MFMA with FP32
+// accumulation (v_mfma_f32_16x16x16_bf16, 64-sample tiles per wave); the
+// 2 -> 64 input layer and the 64 -> 1 output layer are FP32 VALU work (K = 2
+// and N = 1 are not matrix shapes).  It replaces the 2D table inverse CDF of
+// paper Sec. 3.1 / 3.2 inside the trained chi range; the table remains the
+// fallback.
+//
+// Input / output maps (shared by training targets and inference):
+//   x0 = (ln chi - mid) / half, mid/half of ln chi over the trained range.
+//   QS: x1 = 1 + 2 ln u / (-ln u_min); output y -> ln Y = y + 3 ln u with
+//       Y = 2 xi / (3 chi (1 - xi)) (the argument of the Bessel functions of
+//       Sec. 2.2; the cube term is the small-xi law P ~ xi^{1/3}), so
+//       xi = k Y / (1 + k Y), k = 3 chi / 2.
+//   BW: r = min(u, 1 - u) (the fold of Sec. 3.1); x1 = 1 + 2 q / |q(u_min)|
+//       with q = Phi^{-1}(r) the standard-normal quantile; output y -> xi =
+//       1/2 - sigma(chi) y, sigma = s / (1 + 2 s), s = sqrt(3 chi)/8 (the
+//       small-chi width of the pair spectrum about xi = 1/2).
+//   Outside [chi_lo, chi_hi] or for u (r) below u_min the table is used.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,14 +25,152 @@
 namespace qedmi {
 
 constexpr int kHidden = 64;
+constexpr int kNParam = 64 * 2 + 64 + 64 * 64 + 64 + 64 + 1;   // 4417
+constexpr int kOffW1 = 0, kOffB1 = 128, kOffW2 = 192, kOffB2 = 192 + 4096, kOffW3 = kOffB2 + 64,
+              kOffB3 = kOffW3 + 64;
+constexpr float kSurrUMin = 1e-4f;
+constexpr float kBwQMin = 3.7190165f;   // -Phi^{-1}(1e-4)
 
 struct SurrogateDev {
-    int32_t process;            // 0 BW, 1 QS
-    int32_t pad_;
-    float chi_lo, chi_hi;       // trained chi range
-    float x_shift, x_scale;     // x0 = (ln chi - x_shift) * x_scale
+    const float* p;          // FP32 master parameters (layout above)
+    const uint16_t* w2;      // BF16 copy of W2, [n][k] row-major
+    int32_t process;         // 0 BW, 1 QS
+    float mid, inv_half;     // x0 = (ln chi - mid) * inv_half
+    float chi_lo, chi_hi;
     float probe_tol;
-    float pad2_;
 };
+
+typedef short surr_v4s __attribute__((ext_vector_type(4)));
+typedef float surr_v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float surr_silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float surr_dsilu(float z) {
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// FP32 -> BF16 bits, round to nearest even.
+__device__ __forceinline__ short surr_bf16(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<short>(u >> 16);
+}
+
+__device__ __forceinline__ float surr_ndtri_lower(float r) {
+    // Phi^{-1}(r) = -sqrt(2) erfcinv(2 r)
+    return -1.41421356237f * erfcinvf(2.0f * r);
+}
+
+constexpr float kSurrUMaxQs = 1.0f - 1e-5f;   // above: the hard-photon tail goes to the table
+
+// Network features for (chi, u) without domain checks.
+__device__ __forceinline__ void surr_features(const SurrogateDev& s, float chi, float u, float& x0, float& x1) {
+    x0 = (logf(chi) - s.mid) * s.inv_half;
+    if (s.process == 1) {
+        x1 = 1.0f + 2.0f * logf(u) / 9.21034037f;   // -ln(1e-4)
+    } else {
+        const float r = u <= 0.5f ? u : 1.0f - u;
+        x1 = 1.0f + 2.0f * surr_ndtri_lower(r) / kBwQMin;
+    }
+}
+
+// Inside the trained domain?  (Otherwise the table is used.)
+__device__ __forceinline__ bool surr_inside(const SurrogateDev& s, float chi, float u) {
+    if (!(chi >= s.chi_lo && chi <= s.chi_hi)) return false;
+    if (s.process == 1) return u >= kSurrUMin && u <= kSurrUMaxQs;
+    const float r = u <= 0.5f ? u : 1.0f - u;
+    return r >= kSurrUMin;
+}
+
+// Network inputs for (chi, u); returns false if the table must be used.
+__device__ __forceinline__ bool surr_inputs(const SurrogateDev& s, float chi, float u, float& x0, float& x1) {
+    if (!surr_inside(s, chi, u)) return false;
+    surr_features(s, chi, u, x0, x1);
+    return true;
+}
+
+// The network's target for a sample xi of the table (QS: ln xi given), in
+// the output space used by training and by the per-batch probe.
+__device__ __forceinline__ float surr_target_of(int process, float chi, float u, float sample) {
+    if (process == 1) return sample - logf(1.5f * chi) - log1pf(-expf(sample)) - 3.0f * logf(u);
+    const float sc = sqrtf(3.0f * chi) * 0.125f;
+    return (0.5f - sample) / (sc / (1.0f + 2.0f * sc));
+}
+
+__device__ __forceinline__ float surr_bw_sigma(float chi) {
+    const float sc = sqrtf(3.0f * chi) * 0.125f;
+    return sc / (1.0f + 2.0f * sc);
+}
+
+// Network output -> sample: QS returns ln xi, BW returns xi in [0, 1/2].
+__device__ __forceinline__ float surr_output(const SurrogateDev& s, float chi, float u, float y) {
+    if (s.process == 1) {
+        const float lnky = logf(1.5f * chi) + y + 3.0f * logf(u);   // ln(k Y)
+        return -log1pf(expf(-lnky));                                 // ln(kY/(1+kY))
+    }
+    float xi = 0.5f - surr_bw_sigma(chi) * y;
+    return fminf(fmaxf(xi, 0.0f), 0.5f);
+}
+
+// Forward pass for the 64 samples of one wave: lane l owns sample l
+// (inputs x0, x1); returns that sample's output.  lds_y: 64 floats private
+// to the calling wave.  W2 fragments are read from global (L2-resident).
+__device__ __forceinline__ float surr_forward_wave(const SurrogateDev& s, float x0, float x1, float* lds_y) {
+    const int lane = static_cast<int>(__lane_id());
+    const int col = lane & 15, grp = lane >> 4;
+    const float* p = s.p;
+    surr_v4s bw2[4][4];   // B[k][n] = W2[n][k], k = ks*16 + 4 grp + e, n = nt*16 + col
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+            bw2[nt][ks] = *reinterpret_cast<const surr_v4s*>(s.w2 + (nt * 16 + col) * 64 + ks * 16 + 4 * grp);
+    float b2[4], w3[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        b2[nt] = p[kOffB2 + nt * 16 + col];
+        w3[nt] = p[kOffW3 + nt * 16 + col];
+    }
+    const float b3 = p[kOffB3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float sx0 = __shfl(x0, q * 16 + col);
+        const float sx1 = __shfl(x1, q * 16 + col);
+        surr_v4s a[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = ks * 16 + 4 * grp + e;
+                const float z = p[kOffW1 + 2 * k] * sx0 + p[kOffW1 + 2 * k + 1] * sx1 + p[kOffB1 + k];
+                a[ks][e] = surr_bf16(surr_silu(z));
+            }
+        }
+        float part[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            surr_v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[ks], bw2[nt][ks], acc, 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) part[e] += w3[nt] * surr_silu(acc[e] + b2[nt]);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) part[e] += __shfl_xor(part[e], o);
+        }
+        if (col == 0) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) lds_y[q * 16 + 4 * grp + e] = part[e] + b3;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const float y = lds_y[lane];
+    __builtin_amdgcn_wave_barrier();
+    return y;
+}
 
 }  // namespace qedmi
