@@ -97,6 +97,9 @@ def lib():
         L.orc_sample_n.argtypes = [C.POINTER(_Table), C.c_int64, _dp, _dp, _dp, _u8p]
         L.orc_mlp_grad.argtypes = [_dp, C.c_int64, _dp, _dp, _dp, _dp, _dp, i]
         L.orc_mlp_grad.restype = d
+        L.orc_compact.argtypes = [C.c_int64, _i64p, C.POINTER(C.c_int32), C.POINTER(_u8p), _i64p, C.c_int32,
+                                  _i64p, C.c_int64]
+        L.orc_compact.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -355,3 +358,17 @@ def mlp_grad(params, x, t, w=None, bf16=False):
     wp = None if w is None else _ptr(np.ascontiguousarray(w, dtype=np.float64))
     loss = lib().orc_mlp_grad(_ptr(p), len(x), _ptr(x), _ptr(t), wp, _ptr(g), None, int(bf16))
     return loss, g
+
+
+def compact(tiles, set_stream, flags, id_base, stream):
+    """Parent ids of one product stream in (tile, index) order."""
+    tiles = np.ascontiguousarray(tiles, dtype=np.int64).reshape(-1)
+    ss = np.ascontiguousarray(set_stream, dtype=np.int32)
+    fl = [np.ascontiguousarray(f, dtype=np.uint8) for f in flags]
+    fp = (_u8p * len(fl))(*[_ptr(f, _u8p) for f in fl])
+    ib = np.ascontiguousarray(id_base, dtype=np.int64)
+    cap = int(sum(int(f.sum()) for f in fl)) + 1
+    out = np.zeros(cap, dtype=np.int64)
+    k = lib().orc_compact(len(tiles) // 3, _ptr(tiles, _i64p), ss.ctypes.data_as(C.POINTER(C.c_int32)), fp,
+                          _ptr(ib, _i64p), stream, _ptr(out, _i64p), cap)
+    return out[:k]

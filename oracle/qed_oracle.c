@@ -860,3 +860,26 @@ double orc_mlp_grad(const double* p, int64_t n, const double* x, const double* t
     return loss;
 }
 #undef H
+
+/* ------------------------------------------------------------------------ */
+/* Sequential ordered compaction: parent ids of the products of one stream  */
+/* given per-particle event flags, tiles visited in order (tile = set,      */
+/* begin, end), particles in index order inside a tile.  `set_stream[s]`   */
+/* tells which product stream set s feeds (0 leptons, 1 photons, -1 none).  */
+/* Returns the number of parents written (<= cap).                          */
+/* ------------------------------------------------------------------------ */
+int64_t orc_compact(int64_t n_tiles, const int64_t* tiles, const int32_t* set_stream,
+                    const uint8_t* const* flags, const int64_t* id_base, int32_t stream,
+                    int64_t* parents, int64_t cap) {
+    int64_t k = 0;
+    for (int64_t t = 0; t < n_tiles; ++t) {
+        int64_t s = tiles[3 * t], b = tiles[3 * t + 1], e = tiles[3 * t + 2];
+        if (set_stream[s] != stream) continue;
+        for (int64_t i = b; i < e; ++i) {
+            if (!flags[s][i]) continue;
+            if (k < cap) parents[k] = id_base[s] + i;
+            ++k;
+        }
+    }
+    return k;
+}

@@ -185,3 +185,29 @@ def c2_population(seed: int = 1, n: int = 1 << 24, dtype=np.float64):
 
 def subsample(pop: dict, idx: np.ndarray) -> dict:
     return {k: np.ascontiguousarray(v[idx]) for k, v in pop.items()}
+
+
+def fullstep_layout(n_per_species: int, tiles_per_species: int, seed: int = 1, sigma: float = 1.0,
+                    n_species: int = 4) -> np.ndarray:
+    """Tile list (set, begin, end) for n_species sets of n_per_species
+    particles each, every set cut into tiles_per_species lognormal tiles; the
+    list interleaves the sets tile by tile, as the species of one spatial
+    tile of a PIC grid would be visited."""
+    sizes = [lognormal_tiles(n_per_species, tiles_per_species, seed, sigma, stream=s) for s in range(n_species)]
+    offs = [np.concatenate([[0], np.cumsum(z)]) for z in sizes]
+    rows = []
+    for k in range(tiles_per_species):
+        for s in range(n_species):
+            rows.append((s, int(offs[s][k]), int(offs[s][k + 1])))
+    return np.array(rows, dtype=np.int64)
+
+
+def fullstep_population(n_per_species: int, seed: int = 1):
+    """Electrons, positrons, photons (Gaussian pulse fields, FP32) and ions
+    (random FP32 values, passed through untouched)."""
+    el = gaussian_pulse(n_per_species, seed, photon=False, stream=0)
+    po = gaussian_pulse(n_per_species, seed, photon=False, stream=1)
+    ph = gaussian_pulse(n_per_species, seed, photon=True, stream=2)
+    rng = _rng(seed * 4096 + 3)
+    ion = {k: rng.standard_normal(n_per_species).astype(np.float32) for k in FIELDS}
+    return el, po, ph, ion
