@@ -79,6 +79,7 @@ def lib():
         for f in ("orc_chi_lepton", "orc_chi_photon"):
             getattr(L, f).argtypes = [d] * 9; getattr(L, f).restype = d
         L.orc_chi_literal_q.argtypes = [d] * 9 + [i]; L.orc_chi_literal_q.restype = d
+        L.orc_chi_literal_q_n.argtypes = [C.c_int64] + [_dp] * 9 + [i, _dp]
         L.orc_rate_bw.argtypes = [C.POINTER(_Table), d, d]; L.orc_rate_bw.restype = d
         L.orc_rate_qs.argtypes = [C.POINTER(_Table), d, d]; L.orc_rate_qs.restype = d
         L.orc_sample_bw.argtypes = [C.POINTER(_Table), d, d, C.POINTER(C.c_int)]
@@ -100,6 +101,13 @@ def lib():
         L.orc_compact.argtypes = [C.c_int64, _i64p, C.POINTER(C.c_int32), C.POINTER(_u8p), _i64p, C.c_int32,
                                   _i64p, C.c_int64]
         L.orc_compact.restype = C.c_int64
+        L.orc_schwinger_rate.argtypes = [d] * 6; L.orc_schwinger_rate.restype = d
+        L.orc_schwinger_rate_n.argtypes = [C.c_int64] + [_dp] * 7
+        L.orc_schwinger_count.argtypes = [d, C.c_uint64, C.c_uint64, C.c_uint64, _dp]
+        L.orc_schwinger_count.restype = C.c_int64
+        L.orc_schwinger_pairs.argtypes = [C.c_int64] + [_dp] * 6 + [C.c_int64, d, d, d, C.c_uint64, C.c_uint64,
+                                                                 C.POINTER(_Append), C.POINTER(_Append)]
+        L.orc_schwinger_pairs.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -175,6 +183,15 @@ def chi_photon(*a):
 
 def chi_literal_q(*a, photon=False):
     return lib().orc_chi_literal_q(*[float(x) for x in a], int(photon))
+
+
+def chi_literal_q_array(pop: dict, photon: bool) -> np.ndarray:
+    """The printed chi formula in binary128 for every particle of pop."""
+    keys = ("ux", "uy", "uz", "ex", "ey", "ez", "bx", "by", "bz")
+    cols = [np.ascontiguousarray(pop[k], dtype=np.float64) for k in keys]
+    out = np.zeros(len(cols[0]))
+    lib().orc_chi_literal_q_n(len(out), *[_ptr(c) for c in cols], int(photon), _ptr(out))
+    return out
 
 
 def chi_array(pop: dict, photon: bool) -> np.ndarray:
@@ -372,3 +389,34 @@ def compact(tiles, set_stream, flags, id_base, stream):
     k = lib().orc_compact(len(tiles) // 3, _ptr(tiles, _i64p), ss.ctypes.data_as(C.POINTER(C.c_int32)), fp,
                           _ptr(ib, _i64p), stream, _ptr(out, _i64p), cap)
     return out[:k]
+
+
+# ---------------------------------------------------------------- Schwinger
+FIELD_KEYS = ("ex", "ey", "ez", "bx", "by", "bz")
+
+
+def schwinger_rate(ex, ey, ez, bx, by, bz):
+    """Pair production rate per unit volume (m^-3 s^-1) for one field point."""
+    return lib().orc_schwinger_rate(float(ex), float(ey), float(ez), float(bx), float(by), float(bz))
+
+
+def schwinger_rate_array(cells: dict) -> np.ndarray:
+    cols = [np.ascontiguousarray(cells[k], dtype=np.float64) for k in FIELD_KEYS]
+    out = np.zeros(len(cols[0]))
+    lib().orc_schwinger_rate_n(len(out), *[_ptr(c) for c in cols], _ptr(out))
+    return out
+
+
+def schwinger_count(lam, seed, cell, step):
+    """(number of macro-pairs, margin of the deciding comparison)."""
+    m = C.c_double()
+    k = lib().orc_schwinger_count(float(lam), seed, cell, step, C.byref(m))
+    return k, m.value
+
+
+def schwinger_pairs(cells: dict, cell_id_base, dv, dt, weight, seed, step, capacity):
+    cols = [np.ascontiguousarray(cells[k], dtype=np.float64) for k in FIELD_KEYS]
+    el, po = Append(capacity), Append(capacity)
+    lib().orc_schwinger_pairs(len(cols[0]), *[_ptr(c) for c in cols], cell_id_base, dv, dt, weight, seed, step,
+                              el.cstruct, po.cstruct)
+    return el, po

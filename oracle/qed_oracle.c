@@ -762,19 +762,31 @@ void orc_evolve(const orc_table* t, orc_particles* p, double dt, uint8_t* flags)
 void orc_chi_n(int64_t n, const double* ux, const double* uy, const double* uz,
                const double* ex, const double* ey, const double* ez,
                const double* bx, const double* by, const double* bz, int photon, double* out) {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double u[3] = {ux[i], uy[i], uz[i]}, e[3] = {ex[i], ey[i], ez[i]}, b[3] = {bx[i], by[i], bz[i]};
         out[i] = chi_common(u, e, b, photon);
     }
 }
 
+/* binary128 literal chi for n particles (precision studies). */
+void orc_chi_literal_q_n(int64_t n, const double* ux, const double* uy, const double* uz,
+                         const double* ex, const double* ey, const double* ez,
+                         const double* bx, const double* by, const double* bz, int photon, double* out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = orc_chi_literal_q(ux[i], uy[i], uz[i], ex[i], ey[i], ez[i], bx[i], by[i], bz[i], photon);
+}
+
 void orc_rate_n(const orc_table* t, int64_t n, const double* chi, const double* gamma, double* out) {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i)
         out[i] = (t->proc == ORC_BW) ? orc_rate_bw(t, chi[i], gamma[i]) : orc_rate_qs(t, chi[i], gamma[i]);
 }
 
 void orc_sample_n(const orc_table* t, int64_t n, const double* chi, const double* r, double* out,
                   uint8_t* electron_selected) {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         if (t->proc == ORC_BW) {
             int e;
@@ -882,4 +894,99 @@ int64_t orc_compact(int64_t n_tiles, const int64_t* tiles, const int32_t* set_st
         }
     }
     return k;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Schwinger pair production (Sec. 2.3): rate per unit volume               */
+/*   d2N/(dt dV) = q_e^2 E_s^2 / (4 pi^2 hbar^2 c) eps eta coth(pi eta/eps)  */
+/*                 exp(-pi/eps),                                            */
+/* eps = calE/E_s, eta = calH/E_s, calE = sqrt(sqrt(F^2+G^2) + F),          */
+/* calH = sqrt(sqrt(F^2+G^2) - F), F = (E^2 - c^2 B^2)/2, G = c E.B.        */
+/* Evaluated as printed, in binary128.  eta coth(pi eta/eps) tends to       */
+/* eps/pi as eta -> 0; eps = 0 gives rate 0.                                */
+/* ------------------------------------------------------------------------ */
+double orc_schwinger_rate(double ex, double ey, double ez, double bx, double by, double bz) {
+    const __float128 c = ORC_C, es = (__float128)ORC_ME * ORC_ME * c * c * c / ((__float128)ORC_QE * ORC_HBAR);
+    const __float128 pi = M_PIq;
+    const __float128 e2 = (__float128)ex * ex + (__float128)ey * ey + (__float128)ez * ez;
+    const __float128 b2 = (__float128)bx * bx + (__float128)by * by + (__float128)bz * bz;
+    const __float128 F = (e2 - c * c * b2) / 2;
+    const __float128 G = c * ((__float128)ex * bx + (__float128)ey * by + (__float128)ez * bz);
+    const __float128 s = sqrtq(F * F + G * G);
+    const __float128 calE = sqrtq(fmaxq(s + F, 0)), calH = sqrtq(fmaxq(s - F, 0));
+    const __float128 eps = calE / es, eta = calH / es;
+    if (eps == 0) return 0.0;
+    const __float128 pref = (__float128)ORC_QE * ORC_QE * es * es / (4 * pi * pi * (__float128)ORC_HBAR * ORC_HBAR * c);
+    const __float128 x = pi * eta / eps;
+    const __float128 eta_coth = (x == 0) ? eps / pi : eta / tanhq(x);
+    return (double)(pref * eps * eta_coth * expq(-pi / eps));
+}
+
+void orc_schwinger_rate_n(int64_t n, const double* ex, const double* ey, const double* ez, const double* bx,
+                          const double* by, const double* bz, double* out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_schwinger_rate(ex[i], ey[i], ez[i], bx[i], by[i], bz[i]);
+}
+
+/* Macro-pairs created in one cell in one step.  The paper gives the rate and
+ * puts the pairs at rest; the count is this library's reading: Poisson with
+ * mean lambda = rate dV dt / W (W physical pairs per macro-pair), drawn by
+ * inversion with the first uniform of block 0 of the cell's counter
+ * (cell id, step, species 4); for lambda > 25 a Gaussian of mean and
+ * variance lambda (Box-Muller on the first two uniforms), rounded to the
+ * nearest integer and clipped at 0.  `margin` (may be NULL) receives the
+ * distance of the deciding uniform from the nearest CDF boundary (Poisson)
+ * or of the Gaussian value from the nearest half-integer, so that a test can
+ * tell a rounding-level disagreement from a real one. */
+int64_t orc_schwinger_count(double lambda, uint64_t seed, uint64_t cell, uint64_t step, double* margin) {
+    double u[4];
+    orc_draws(seed, cell, step, 4, 0, u);
+    if (!(lambda > 0.0)) {
+        if (margin) *margin = INFINITY;
+        return 0;
+    }
+    if (lambda <= 25.0) {
+        double p = exp(-lambda), cum = p, m = fabs(u[0] - cum);
+        int64_t k = 0;
+        while (u[0] > cum && k < 1000) {
+            ++k;
+            p *= lambda / (double)k;
+            cum += p;
+            if (fabs(u[0] - cum) < m) m = fabs(u[0] - cum);
+        }
+        if (margin) *margin = m;
+        return k;
+    }
+    const double z = sqrt(-2.0 * log(u[0])) * cos(2.0 * M_PI * u[1]);
+    const double v = lambda + sqrt(lambda) * z;
+    if (margin) *margin = fabs(v - floor(v) - 0.5);
+    if (v < 0.5) return 0;
+    return (int64_t)floor(v + 0.5);
+}
+
+/* Pairs for n cells, appended in cell order (electron and positron of the
+ * same pair share a slot index in their buffers): momentum 0 (at rest),
+ * weight W, optical depth -ln u from the pair's own block (cell, step,
+ * species 4, block 1 + i/2: uniforms 2(i%2) and 2(i%2)+1 for the electron
+ * and the positron of pair i).  Returns the number of pairs. */
+int64_t orc_schwinger_pairs(int64_t n, const double* ex, const double* ey, const double* ez, const double* bx,
+                            const double* by, const double* bz, int64_t cell_id_base, double dv, double dt,
+                            double weight, uint64_t seed, uint64_t step, orc_append* el, orc_append* po) {
+    int64_t total = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double lam = orc_schwinger_rate(ex[i], ey[i], ez[i], bx[i], by[i], bz[i]) * dv * dt / weight;
+        const uint64_t cell = (uint64_t)(cell_id_base + i);
+        const int64_t k = orc_schwinger_count(lam, seed, cell, step, NULL);
+        for (int64_t q = 0; q < k; ++q) {
+            double u[4];
+            orc_draws(seed, cell, step, 4, (uint64_t)(1 + q / 2), u);
+            const int h = (int)(q % 2);
+            put(el, total, 0.0, 0.0, 0.0, weight, -log(u[2 * h]), cell_id_base + i);
+            put(po, total, 0.0, 0.0, 0.0, weight, -log(u[2 * h + 1]), cell_id_base + i);
+            ++total;
+        }
+    }
+    el->count = total;
+    po->count = total;
+    return total;
 }

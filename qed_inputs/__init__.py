@@ -211,3 +211,15 @@ def fullstep_population(n_per_species: int, seed: int = 1):
     rng = _rng(seed * 4096 + 3)
     ion = {k: rng.standard_normal(n_per_species).astype(np.float32) for k in FIELDS}
     return el, po, ph, ion
+
+
+def uniforms(n: int, seed: int, stream: int = 0) -> np.ndarray:
+    """n uniforms in the open interval (0, 1) (inverse-CDF sampling inputs)."""
+    rng = _rng(seed * 4096 + 3072 + stream)
+    u = rng.random(n)
+    return np.where(u > 0.0, u, 2.0 ** -54)
+
+
+def loguniform_chi(n: int, seed: int, lo: float, hi: float, stream: int = 0) -> np.ndarray:
+    """n quantum parameters log-uniform in [lo, hi]."""
+    return _loguniform(_rng(seed * 4096 + 3584 + stream), lo, hi, n)
