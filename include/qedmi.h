@@ -200,7 +200,9 @@ int32_t qed_table_rate(const qed_table* t, int32_t dtype, const void* chi, const
 
 /* Inverse-CDF sample for n (chi, u) pairs, u in (0, 1) (Sec. 3.1 / 3.2
  * sampling).  BW: out = xi in [0, 1/2], electron_selected[i] = (u <= 1/2)
- * (may be NULL).  QS: out = ln xi.  Device arrays of `dtype`. */
+ * (may be NULL).  QS: out = ln xi.  Device arrays of `dtype`.
+ * For both calls dtype QED_BF16 means FP32 arrays and FP32 arithmetic on the
+ * BF16-stored copies of the tables (precision studies). */
 int32_t qed_table_sample(const qed_table* t, int32_t dtype, const void* chi, const void* u, void* out,
                          uint8_t* electron_selected, int64_t n, void* stream);
 
@@ -303,6 +305,45 @@ int32_t qed_surrogate_grad(const qed_surrogate* s, const float* x, const float* 
 int32_t qed_surrogate_sample(const qed_surrogate* s, const float* chi, const float* u, float* out,
                              int64_t n, void* stream);
 void qed_surrogate_destroy(qed_surrogate* s);
+
+/* ---------------------------------------------------------------- Schwinger
+ * Pair creation from the vacuum by a strong field (Sec. 2.3).  Works on
+ * field values per grid cell rather than on particles. */
+typedef struct {
+    const void *ex, *ey, *ez;   /* device arrays, V/m, one entry per cell  */
+    const void *bx, *by, *bz;   /* device arrays, T                        */
+    int64_t n;                  /* number of cells (>= 0)                  */
+    int64_t cell_id_base;       /* global id of cell 0: Philox counter and
+                                   the products' parent id                 */
+    int32_t dtype;              /* QED_FP64 or QED_FP32                    */
+    int32_t pad_;
+} qed_cells;
+
+/* Pair production rate per unit volume d2N/(dt dV) in m^-3 s^-1 for every
+ * cell, from the field invariants F = (E^2 - c^2 B^2)/2 and G = c E.B
+ * (Sec. 2.3 rate formula).  rate_out: device FP64 array of n entries
+ * (rates near E_s exceed the FP32 range in SI units), also for FP32 fields.
+ * Arithmetic in FP64; the invariants are formed on fields scaled
+ * by E_s and without subtracting sqrt(F^2 + G^2) from |F|.  A field with no
+ * invariant electric part (pure magnetic, crossed |E| = c|B|) gives 0. */
+int32_t qed_schwinger_rate(qed_context* ctx, const qed_cells* cells, void* rate_out, void* stream);
+
+/* Macro-pairs created at rest (Sec. 2.3: pairs may be initialised at rest).
+ * The paper gives the rate only; the count per cell is this library's
+ * choice: Poisson with mean lambda = rate * cell_volume * dt / weight
+ * (inversion with the first uniform of counter (cell id, step, 4, 0)), and
+ * for lambda > 25 a Gaussian of mean and variance lambda rounded to the
+ * nearest integer and clipped at 0.  Pairs are appended to `electrons` and
+ * `positrons` in cell order after their current counts (the two members of a
+ * pair at the same offset), with u = 0, w = weight, parent = cell id and
+ * tau = -ln u from counter (cell id, step, 4, 1 + i/2) (uniforms 2(i%2) and
+ * 2(i%2)+1 of pair i).  The counts are incremented on the device; capacity
+ * contract as for qed_step (pairs beyond capacity are not written; check
+ * with qed_read_count).  Buffers must have dtype = cells->dtype.
+ * cell_volume in m^3, dt in s, weight = physical pairs per macro-pair > 0. */
+int32_t qed_schwinger_pairs(qed_context* ctx, const qed_cells* cells, double cell_volume, double dt,
+                            double weight, uint64_t seed, uint64_t step, qed_append* electrons,
+                            qed_append* positrons, void* stream);
 
 /* ------------------------------------------------------------------- misc */
 const char* qed_last_error(void);

@@ -34,6 +34,7 @@ EXPORTS = (
     "qed_table_rate", "qed_table_sample",
     "qed_surrogate_train", "qed_surrogate_from_host", "qed_surrogate_get_params",
     "qed_surrogate_forward", "qed_surrogate_grad", "qed_surrogate_sample", "qed_surrogate_destroy",
+    "qed_schwinger_rate", "qed_schwinger_pairs",
     "qed_last_error", "qed_version",
 )
 
@@ -69,6 +70,11 @@ class StepDescC(C.Structure):
                 ("flags", C.POINTER(C.c_void_p)), ("stats", C.c_void_p), ("dt", C.c_double),
                 ("seed", C.c_uint64), ("step", C.c_uint64), ("photon_min_energy", C.c_double),
                 ("chi_mode", C.c_int32), ("pad_", C.c_int32)]
+
+
+class CellsC(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("ex", "ey", "ez", "bx", "by", "bz")] + \
+               [("n", C.c_int64), ("cell_id_base", C.c_int64), ("dtype", C.c_int32), ("pad_", C.c_int32)]
 
 
 class SurrogateCfg(C.Structure):
@@ -114,6 +120,8 @@ def lib():
             "qed_surrogate_forward": [vp, vp, vp, i64, vp],
             "qed_surrogate_grad": [vp, vp, vp, i64, vp, vp, vp],
             "qed_surrogate_sample": [vp, vp, vp, vp, i64, vp],
+            "qed_schwinger_rate": [vp, P(CellsC), vp, vp],
+            "qed_schwinger_pairs": [vp, P(CellsC), d, d, d, u64, u64, P(AppendC), P(AppendC), vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -211,13 +219,14 @@ class Context:
             self.h = None
 
 
-def table_rate(table: Table, chi, gamma, out, stream=None):
-    check(lib().qed_table_rate(table.h, dtype_code(chi), _ptr(chi), _ptr(gamma), _ptr(out), chi.numel(),
-                               _stream(stream)))
+def table_rate(table: Table, chi, gamma, out, stream=None, bf16_tables=False):
+    dt = BF16 if bf16_tables else dtype_code(chi)
+    check(lib().qed_table_rate(table.h, dt, _ptr(chi), _ptr(gamma), _ptr(out), chi.numel(), _stream(stream)))
 
 
-def table_sample(table: Table, chi, u, out, electron_selected=None, stream=None):
-    check(lib().qed_table_sample(table.h, dtype_code(chi), _ptr(chi), _ptr(u), _ptr(out), _ptr(electron_selected),
+def table_sample(table: Table, chi, u, out, electron_selected=None, stream=None, bf16_tables=False):
+    dt = BF16 if bf16_tables else dtype_code(chi)
+    check(lib().qed_table_sample(table.h, dt, _ptr(chi), _ptr(u), _ptr(out), _ptr(electron_selected),
                                  chi.numel(), _stream(stream)))
 
 
@@ -391,3 +400,21 @@ class Surrogate:
         if getattr(self, "h", None) is not None and self.h.value and _lib is not None:
             _lib.qed_surrogate_destroy(self.h)
             self.h = None
+
+
+# ---------------------------------------------------------------- Schwinger
+def cells(d: dict, cell_id_base=0) -> CellsC:
+    """Cell view of device field tensors ex, ey, ez, bx, by, bz (one dtype)."""
+    t = d["ex"]
+    return CellsC(*[_ptr(d[k]) for k in ("ex", "ey", "ez", "bx", "by", "bz")], t.numel(), int(cell_id_base),
+                  dtype_code(t), 0)
+
+
+def schwinger_rate(ctx, c: CellsC, rate_out, stream=None):
+    check(lib().qed_schwinger_rate(ctx.h, C.byref(c), _ptr(rate_out), _stream(stream)))
+
+
+def schwinger_pairs(ctx, c: CellsC, cell_volume, dt, weight, seed, step, electrons: AppendBuffer,
+                    positrons: AppendBuffer, stream=None):
+    check(lib().qed_schwinger_pairs(ctx.h, C.byref(c), float(cell_volume), float(dt), float(weight), seed, step,
+                                    C.byref(electrons.c), C.byref(positrons.c), _stream(stream)))

@@ -120,6 +120,31 @@ int32_t reserve(qed_context* ctx, int64_t n_chunks) {
     return QED_OK;
 }
 
+}  // namespace
+
+namespace qedmi {
+int32_t check_append_dtype(const qed_append* a, int dtype, const char* name) { return check_append(a, dtype, name); }
+AppendDev append_view(const qed_append* a) { return to_append(a); }
+
+// Grow the context's general scratch to at least `bytes` (contents undefined).
+int32_t reserve_scratch(qed_context* ctx, int64_t bytes) {
+    if (bytes <= ctx->scratch_cap) return QED_OK;
+    const int64_t cap = std::max<int64_t>(bytes, 2 * ctx->scratch_cap);
+    void* p = nullptr;
+    if (hipMalloc(&p, static_cast<size_t>(cap)) != hipSuccess) {
+        set_error("device allocation of scratch failed");
+        return QED_ERR_ALLOC;
+    }
+    hipDeviceSynchronize();   // queued work may still use the old buffer
+    hipFree(ctx->d_scratch);
+    ctx->d_scratch = p;
+    ctx->scratch_cap = cap;
+    return QED_OK;
+}
+}  // namespace qedmi
+
+namespace {
+
 // Build chunks ordered by (stream, tile order) and upload them if they
 // differ from the cached table.
 int32_t build_chunks(qed_context* ctx, const std::vector<SetDev>& sets, const int64_t* tiles, int n_tiles,
@@ -185,7 +210,7 @@ int32_t launch_chunks(qed_context* ctx, StepArgs& a, int dtype, hipStream_t s) {
     int dev = 0;
     hipGetDevice(&dev);
     if (dev != ctx->device) { set_error("context belongs to another device"); return QED_ERR_INVALID; }
-    const int grid = std::max(1, std::min(a.n_chunks, step_grid_size(dtype, a.use_bw_surr || a.use_qs_surr, ctx->device)));
+    const int grid = std::max(1, std::min(a.n_chunks, step_grid_size(a, dtype, ctx->device)));
     ctx->epoch = ctx->epoch + 1 == 0 ? 1 : ctx->epoch + 1;
     a.status = ctx->d_status;
     a.ticket = ctx->d_ticket;
@@ -239,6 +264,7 @@ extern "C" void qed_context_destroy(qed_context* c) {
     hipFree(c->d_ticket);
     hipFree(c->d_status);
     hipFree(c->d_chunks);
+    hipFree(c->d_scratch);
     hipSetDevice(cur);
     delete c;
 }
@@ -420,7 +446,10 @@ static int32_t table_call(const qed_table* t, int32_t dtype, const void* a, cons
                           int64_t n, void* stream, bool sample) {
     if (!t) { set_error("table is null"); return QED_ERR_INVALID; }
     if (t->device < 0 || !t->d_ln_rate64) { set_error("table is not on the device"); return QED_ERR_STATE; }
-    if (dtype != QED_FP64 && dtype != QED_FP32) { set_error("dtype must be FP64 or FP32"); return QED_ERR_INVALID; }
+    if (dtype != QED_FP64 && dtype != QED_FP32 && dtype != QED_BF16) {
+        set_error("dtype must be FP64, FP32 or BF16");
+        return QED_ERR_INVALID;
+    }
     if (n < 0) { set_error("n < 0"); return QED_ERR_INVALID; }
     if (n == 0) return QED_OK;
     if (!a || !b || !out) { set_error("null array"); return QED_ERR_INVALID; }

@@ -247,41 +247,57 @@ __device__ __forceinline__ void grid_pos(const TableDev& t, T lnchi, int& n, T& 
     f = x - static_cast<T>(k);
 }
 
+// BF16 table storage, read as FP32 (precision studies).
+struct Bf16 {
+    uint16_t bits;
+};
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(static_cast<unsigned>(b) << 16); }
+
+// Table element of storage type S read as arithmetic type T.
+template <typename T>
+__device__ __forceinline__ T tload(const double* p, int i) { return static_cast<T>(p[i]); }
+template <typename T>
+__device__ __forceinline__ T tload(const float* p, int i) { return static_cast<T>(p[i]); }
+template <typename T>
+__device__ __forceinline__ T tload(const Bf16* p, int i) { return static_cast<T>(bf16_to_f32(p[i].bits)); }
+
 // BW: dN/dt = (alpha m c^2/hbar) (chi_gamma/gamma_gamma) T(chi_gamma)
 // (Sec. 2.1); ln T interpolated linearly in ln chi (Sec. 3.1); outside the
 // table, the asymptotes of the integral definition matched at the edges:
 // ln T - (8/3)(1/chi - 1/chi_min) below, ln T - (1/3) ln(chi/chi_max) above.
-template <typename T>
-__device__ __forceinline__ T rate_bw(const T* ln_t, const TableDev& t, T chi, T gamma_g) {
+template <typename T, typename S>
+__device__ __forceinline__ T rate_bw(const S* ln_t, const TableDev& t, T chi, T gamma_g) {
     if (!(chi > T(0)) || !(gamma_g > T(0))) return T(0);
     T y;
     if (chi < static_cast<T>(t.chi_min)) {
-        y = ln_t[0] - T(8.0 / 3.0) * (T(1) / chi - static_cast<T>(1.0 / t.chi_min));
+        y = tload<T>(ln_t, 0) - T(8.0 / 3.0) * (T(1) / chi - static_cast<T>(1.0 / t.chi_min));
     } else if (chi > static_cast<T>(t.chi_max)) {
-        y = ln_t[t.n_chi - 1] - T(1.0 / 3.0) * (dlog(chi) - static_cast<T>(log(t.chi_max)));
+        y = tload<T>(ln_t, t.n_chi - 1) - T(1.0 / 3.0) * (dlog(chi) - static_cast<T>(log(t.chi_max)));
     } else {
         int n;
         T f;
         grid_pos<T>(t, dlog(chi), n, f);
-        y = ln_t[n] + f * (ln_t[n + 1] - ln_t[n]);
+        const T y0 = tload<T>(ln_t, n), y1 = tload<T>(ln_t, n + 1);
+        y = y0 + f * (y1 - y0);
     }
     return static_cast<T>(kRateR0) * (chi / gamma_g) * dexp(y);
 }
 
 // QS: dN/dt = (2/3)(alpha m c^2/hbar) G(chi)/gamma (Sec. 2.2); ln G
 // interpolated in ln chi; first/last stored value outside (Sec. 3.2).
-template <typename T>
-__device__ __forceinline__ T rate_qs(const T* ln_g, const TableDev& t, T chi, T gamma) {
+template <typename T, typename S>
+__device__ __forceinline__ T rate_qs(const S* ln_g, const TableDev& t, T chi, T gamma) {
     T y;
     if (!(chi >= static_cast<T>(t.chi_min))) {
-        y = ln_g[0];
+        y = tload<T>(ln_g, 0);
     } else if (chi > static_cast<T>(t.chi_max)) {
-        y = ln_g[t.n_chi - 1];
+        y = tload<T>(ln_g, t.n_chi - 1);
     } else {
         int n;
         T f;
         grid_pos<T>(t, dlog(chi), n, f);
-        y = ln_g[n] + f * (ln_g[n + 1] - ln_g[n]);
+        const T y0 = tload<T>(ln_g, n), y1 = tload<T>(ln_g, n + 1);
+        y = y0 + f * (y1 - y0);
     }
     return static_cast<T>(2.0 / 3.0 * kRateR0) * dexp(y) / gamma;
 }
@@ -295,17 +311,22 @@ __device__ __forceinline__ void row_pos(const TableDev& t, T chi, int& n, T& f) 
     grid_pos<T>(t, dlog(c), n, f);
 }
 
-template <typename T>
-__device__ __forceinline__ const T* cdf_ptr(const TableDev& t);
+template <typename S>
+__device__ __forceinline__ const S* cdf_ptr(const TableDev& t);
 template <>
 __device__ __forceinline__ const double* cdf_ptr<double>(const TableDev& t) { return t.cdf64; }
 template <>
 __device__ __forceinline__ const float* cdf_ptr<float>(const TableDev& t) { return t.cdf32; }
+template <>
+__device__ __forceinline__ const Bf16* cdf_ptr<Bf16>(const TableDev& t) {
+    return reinterpret_cast<const Bf16*>(t.cdf16);
+}
+
 
 // BW pair sampling (Sec. 3.1): r <= 1/2 selects the electron, otherwise
 // r -> 1 - r selects the positron; rows n, n+1 interpolated in ln chi_gamma;
 // binary search for P_m <= r < P_{m+1}; linear inverse in xi.
-template <typename T>
+template <typename T, typename S = T>
 __device__ __forceinline__ T sample_bw(const TableDev& t, T chi, T r, bool& electron) {
     int n;
     T f;
@@ -313,16 +334,16 @@ __device__ __forceinline__ T sample_bw(const TableDev& t, T chi, T r, bool& elec
     electron = (r <= T(0.5));
     if (!electron) r = T(1) - r;
     const int nf = t.n_frac;
-    const T* p0 = cdf_ptr<T>(t) + static_cast<size_t>(n) * nf;
-    const T* p1 = p0 + nf;
+    const S* p0 = cdf_ptr<S>(t) + static_cast<size_t>(n) * nf;
+    const S* p1 = p0 + nf;
     int lo = 0, hi = nf - 1;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        const T pm = p0[mid] + f * (p1[mid] - p0[mid]);
+        const T pm = tload<T>(p0, mid) + f * (tload<T>(p1, mid) - tload<T>(p0, mid));
         if (pm <= r) lo = mid; else hi = mid;
     }
-    const T pa = p0[lo] + f * (p1[lo] - p0[lo]);
-    const T pb = p0[lo + 1] + f * (p1[lo + 1] - p0[lo + 1]);
+    const T pa = tload<T>(p0, lo) + f * (tload<T>(p1, lo) - tload<T>(p0, lo));
+    const T pb = tload<T>(p0, lo + 1) + f * (tload<T>(p1, lo + 1) - tload<T>(p0, lo + 1));
     const T scale = T(0.5) / static_cast<T>(nf - 1);
     const T xa = scale * static_cast<T>(lo), xb = scale * static_cast<T>(lo + 1);
     return xa + (r - pa) * (xb - xa) / (pb - pa);
@@ -332,26 +353,26 @@ __device__ __forceinline__ T sample_bw(const TableDev& t, T chi, T r, bool& elec
 // search on ln r; log-log inverse.  Below the first knot the small-xi law
 // P ~ xi^{1/3} continues the table: ln xi = ln xi_min + 3 (ln r - ln P_0).
 // Returns ln xi.
-template <typename T>
+template <typename T, typename S = T>
 __device__ __forceinline__ T sample_qs_lnxi(const TableDev& t, T chi, T r) {
     int n;
     T f;
     row_pos<T>(t, chi, n, f);
     const int nf = t.n_frac;
-    const T* p0 = cdf_ptr<T>(t) + static_cast<size_t>(n) * nf;
-    const T* p1 = p0 + nf;
+    const S* p0 = cdf_ptr<S>(t) + static_cast<size_t>(n) * nf;
+    const S* p1 = p0 + nf;
     const T lr = dlog(r);
     const T lmin = static_cast<T>(t.ln_frac_min);
-    const T l0 = p0[0] + f * (p1[0] - p0[0]);
+    const T l0 = tload<T>(p0, 0) + f * (tload<T>(p1, 0) - tload<T>(p0, 0));
     if (lr < l0) return lmin + T(3) * (lr - l0);
     int lo = 0, hi = nf - 1;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        const T lm = p0[mid] + f * (p1[mid] - p0[mid]);
+        const T lm = tload<T>(p0, mid) + f * (tload<T>(p1, mid) - tload<T>(p0, mid));
         if (lm <= lr) lo = mid; else hi = mid;
     }
-    const T la = p0[lo] + f * (p1[lo] - p0[lo]);
-    const T lb = p0[lo + 1] + f * (p1[lo + 1] - p0[lo + 1]);
+    const T la = tload<T>(p0, lo) + f * (tload<T>(p1, lo) - tload<T>(p0, lo));
+    const T lb = tload<T>(p0, lo + 1) + f * (tload<T>(p1, lo + 1) - tload<T>(p0, lo + 1));
     const T inv = T(1) / static_cast<T>(nf - 1);
     const T xa = lmin * (T(1) - static_cast<T>(lo) * inv);
     const T xb = lmin * (T(1) - static_cast<T>(lo + 1) * inv);

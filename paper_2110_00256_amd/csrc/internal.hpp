@@ -28,6 +28,7 @@ struct TableDev {
     const double* cdf64;
     const float* ln_rate32;
     const float* cdf32;
+    const uint16_t* ln_rate16;
     const uint16_t* cdf16;
     int32_t n_chi, n_frac;
     double chi_min, chi_max;
@@ -98,7 +99,7 @@ hipError_t launch_step(const StepArgs& a, int dtype, int grid, hipStream_t s);
 hipError_t launch_chi(const ElemArgs& a, int dtype, hipStream_t s);
 hipError_t launch_init_tau(const ElemArgs& a, int dtype, hipStream_t s);
 hipError_t launch_evolve(const ElemArgs& a, int dtype, hipStream_t s);
-int step_grid_size(int dtype, bool surr, int device);
+int step_grid_size(const StepArgs& a, int dtype, int device);
 
 struct TableCallArgs {
     TableDev table;
@@ -122,6 +123,7 @@ struct qed_table {
     double* d_cdf64 = nullptr;
     float* d_ln_rate32 = nullptr;
     float* d_cdf32 = nullptr;
+    uint16_t* d_ln_rate16 = nullptr;
     uint16_t* d_cdf16 = nullptr;
     qedmi::TableDev view() const;
 };
@@ -137,4 +139,13 @@ struct qed_context {
     qedmi::ChunkDesc* d_chunks = nullptr;
     int64_t chunks_cap = 0;
     std::vector<qedmi::ChunkDesc> h_chunks_cached;
+    void* d_scratch = nullptr;              // general device scratch (Schwinger scan offsets)
+    int64_t scratch_cap = 0;                // bytes
 };
+
+namespace qedmi {
+// Shared by the C-ABI translation units (defined in api.cpp).
+int32_t check_append_dtype(const qed_append* a, int dtype, const char* name);
+AppendDev append_view(const qed_append* a);
+int32_t reserve_scratch(qed_context* ctx, int64_t bytes);
+}  // namespace qedmi

@@ -44,6 +44,17 @@ template <typename T>
 __device__ __forceinline__ void st(void* p, int64_t i, T v) {
     static_cast<T*>(p)[i] = v;
 }
+// Streaming (non-temporal) access for the particle stream: every element is
+// touched once per step, so it should not evict the lookup tables that the
+// inverse-CDF search walks from L2.
+template <typename T>
+__device__ __forceinline__ T ldnt(const void* p, int64_t i) {
+    return __builtin_nontemporal_load(static_cast<const T*>(p) + i);
+}
+template <typename T>
+__device__ __forceinline__ void stnt(void* p, int64_t i, T v) {
+    __builtin_nontemporal_store(v, static_cast<T*>(p) + i);
+}
 
 template <typename T>
 __device__ __forceinline__ const T* ln_rate_ptr(const TableDev& t);
@@ -148,31 +159,21 @@ __device__ __forceinline__ float surr_wave_sample(const StepArgs& a, const Surro
     return surr_output(sv, chi, u, y);
 }
 
-// Sampled photon fraction ln xi for a lepton event: surrogate (FP32 data)
-// or table.  Called by all lanes of the wave.
-template <typename T, bool kSurr>
-__device__ __forceinline__ T qs_lnxi(const StepArgs& a, bool valid, T chi, T r, float* lds_y) {
-    if constexpr (kSurr && sizeof(T) == 4) {
-        if (a.use_qs_surr) {
-            const float v = surr_wave_sample(a, a.qs_surr, a.qs, valid, chi, r, lds_y, a.stats);
-            if (!__builtin_isnan(v)) return v;
-        }
-    }
-    return valid ? dev::sample_qs_lnxi<T>(a.qs, chi, r) : T(0);
+// Sampled photon fraction ln xi for a lepton event.  `cs` is the event's
+// LDS word: the surrogate's sample when `have`, else chi for the table.
+template <typename T>
+__device__ __forceinline__ T qs_lnxi(const StepArgs& a, bool valid, bool have, T cs, T r) {
+    if (have) return cs;
+    return valid ? dev::sample_qs_lnxi<T>(a.qs, cs, r) : T(0);
 }
 
-// Pair fraction xi (electron_selected out) for a photon event.
-template <typename T, bool kSurr>
-__device__ __forceinline__ T bw_xi(const StepArgs& a, bool valid, T chi, T r, bool& esel, float* lds_y) {
+// Pair fraction xi (electron_selected out) for a photon event; `cs` as above.
+template <typename T>
+__device__ __forceinline__ T bw_xi(const StepArgs& a, bool valid, bool have, T cs, T r, bool& esel) {
     esel = r <= T(0.5);
-    if constexpr (kSurr && sizeof(T) == 4) {
-        if (a.use_bw_surr) {
-            const float v = surr_wave_sample(a, a.bw_surr, a.bw, valid, chi, r, lds_y, a.stats);
-            if (!__builtin_isnan(v)) return v;
-        }
-    }
+    if (have) return cs;
     bool e;
-    return valid ? dev::sample_bw<T>(a.bw, chi, r, e) : T(0);
+    return valid ? dev::sample_bw<T>(a.bw, cs, r, e) : T(0);
 }
 
 // Per-event state shared by the two passes over a chunk's events.
@@ -184,29 +185,30 @@ struct EventCtx {
     dev::Draws d;
 };
 
-template <typename T, bool kPhoton, int kChiMode>
-__device__ __forceinline__ EventCtx<T> load_event(const StepArgs& a, const SetDev& S, int64_t j) {
+// Event state: the momentum is gathered again, chi (or the surrogate's
+// sample) comes from the LDS word written earlier, gamma and |u|^2 are
+// recomputed from u.
+template <typename T, bool kPhoton>
+__device__ __forceinline__ EventCtx<T> load_event(const StepArgs& a, const SetDev& S, int64_t j, T chi) {
     EventCtx<T> e;
     e.j = j;
     e.ux = ld<T>(S.p[0], j);
     e.uy = ld<T>(S.p[1], j);
     e.uz = ld<T>(S.p[2], j);
-    const dev::ChiGamma cg = dev::chi_of<T, kPhoton>(kChiMode, e.ux, e.uy, e.uz, ld<T>(S.p[3], j),
-                                                     ld<T>(S.p[4], j), ld<T>(S.p[5], j), ld<T>(S.p[6], j),
-                                                     ld<T>(S.p[7], j), ld<T>(S.p[8], j));
-    e.chi = cg.chi;
-    e.gamma = cg.gamma;
-    e.u2 = cg.u2;
+    const double ux = e.ux, uy = e.uy, uz = e.uz;
+    e.u2 = ux * ux + uy * uy + uz * uz;
+    e.gamma = kPhoton ? sqrt(e.u2) : sqrt(1.0 + e.u2);
+    e.chi = chi;
     e.d = dev::draws(a.seed, static_cast<unsigned long long>(S.id_base + j), a.step,
                      static_cast<unsigned long long>(S.species), 0ULL);
     return e;
 }
 
 // QS photon energy gamma_gamma = (gamma - 1) xi, with gamma - 1 = |u|^2/(gamma + 1).
-template <typename T, bool kSurr>
-__device__ __forceinline__ T qs_photon_energy(const StepArgs& a, bool valid, const EventCtx<T>& e, T& xi_out,
-                                              float* lds_y) {
-    const T lnxi = qs_lnxi<T, kSurr>(a, valid, static_cast<T>(e.chi), static_cast<T>(e.d.u[0]), lds_y);
+template <typename T>
+__device__ __forceinline__ T qs_photon_energy(const StepArgs& a, bool valid, bool have, const EventCtx<T>& e,
+                                              T& xi_out) {
+    const T lnxi = qs_lnxi<T>(a, valid, have, static_cast<T>(e.chi), static_cast<T>(e.d.u[0]));
     const T xi = dev::dexp(lnxi);
     xi_out = xi;
     return static_cast<T>(e.u2 / (e.gamma + 1.0)) * xi;
@@ -220,8 +222,10 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
     T* t_bw = reinterpret_cast<T*>(lds_raw);
     T* t_qs = t_bw + ((nbw + 1) & ~1);
     uint16_t* evlist = reinterpret_cast<uint16_t*>(t_qs + ((nqs + 1) & ~1));
+    T* s_chi = reinterpret_cast<T*>(evlist + kChunk);   // chi of every particle of the chunk
     __shared__ unsigned long long emask[kChunk / 64];
     __shared__ unsigned long long kmask[kChunk / 64];
+    __shared__ unsigned long long smask[kSurr ? kChunk / 64 : 1];   // events sampled by the surrogate
     __shared__ int epref[kChunk / 64];
     __shared__ int kpref[kChunk / 64];
     __shared__ int s_ticket, s_total, s_kept;
@@ -258,34 +262,68 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
 
         // ---------------- phase 1: stream, evolve, flag
         const T dt = static_cast<T>(a.dt);
-        for (int it = 0; it < kChunk / kBlock; ++it) {
-            const int loc = it * kBlock + tid;
-            bool ev = false;
-            if (loc < c.len) {
-                const int64_t j = c.begin + loc;
-                if (a.generate_only) {
+        if (a.generate_only) {
+            for (int it = 0; it < kChunk / kBlock; ++it) {
+                const int loc = it * kBlock + tid;
+                bool ev = false;
+                if (loc < c.len) {
+                    const int64_t j = c.begin + loc;
                     ev = S.flags[j] != 0;
-                } else {
-                    const T ux = ld<T>(S.p[0], j), uy = ld<T>(S.p[1], j), uz = ld<T>(S.p[2], j);
-                    const T ex = ld<T>(S.p[3], j), ey = ld<T>(S.p[4], j), ez = ld<T>(S.p[5], j);
-                    const T bx = ld<T>(S.p[6], j), by = ld<T>(S.p[7], j), bz = ld<T>(S.p[8], j);
-                    const T tau = ld<T>(S.p[9], j);
-                    T rate;
-                    if (photon) {
-                        const dev::ChiGamma cg = dev::chi_of<T, true>(kChiMode, ux, uy, uz, ex, ey, ez, bx, by, bz);
-                        rate = dev::rate_bw<T>(t_bw, a.bw, static_cast<T>(cg.chi), static_cast<T>(cg.gamma));
-                    } else {
-                        const dev::ChiGamma cg = dev::chi_of<T, false>(kChiMode, ux, uy, uz, ex, ey, ez, bx, by, bz);
-                        rate = dev::rate_qs<T>(t_qs, a.qs, static_cast<T>(cg.chi), static_cast<T>(cg.gamma));
+                    if (ev) {
+                        const T ux = ld<T>(S.p[0], j), uy = ld<T>(S.p[1], j), uz = ld<T>(S.p[2], j);
+                        const T ex = ld<T>(S.p[3], j), ey = ld<T>(S.p[4], j), ez = ld<T>(S.p[5], j);
+                        const T bx = ld<T>(S.p[6], j), by = ld<T>(S.p[7], j), bz = ld<T>(S.p[8], j);
+                        s_chi[loc] = photon
+                            ? static_cast<T>(dev::chi_of<T, true>(kChiMode, ux, uy, uz, ex, ey, ez, bx, by, bz).chi)
+                            : static_cast<T>(dev::chi_of<T, false>(kChiMode, ux, uy, uz, ex, ey, ez, bx, by, bz).chi);
                     }
-                    const T tn = tau - rate * dt;
-                    ev = tn < T(0);
-                    if (!ev) st<T>(S.p[9], j, tn);
-                    if (S.flags) S.flags[j] = static_cast<uint8_t>(ev);
+                }
+                const unsigned long long m = __ballot(ev);
+                if (lane == 0) emask[it * (kBlock / 64) + wave] = m;
+            }
+        } else {
+            // kBatch particles per thread have all their loads in flight
+            // before any of them is evaluated (stores in between could alias
+            // the next loads, so the compiler would not hoist them itself).
+            // Lanes past the end load the chunk's first particle and drop it.
+            constexpr int kBatch = sizeof(T) == 8 ? 2 : 4;
+            for (int it = 0; it < kChunk / kBlock; it += kBatch) {
+                T v[kBatch][10];
+#pragma unroll
+                for (int b = 0; b < kBatch; ++b) {
+                    const int loc = (it + b) * kBlock + tid;
+                    const int64_t j = c.begin + (loc < c.len ? loc : 0);
+#pragma unroll
+                    for (int q = 0; q < 10; ++q) v[b][q] = ldnt<T>(S.p[q], j);
+                }
+#pragma unroll
+                for (int b = 0; b < kBatch; ++b) {
+                    const int loc = (it + b) * kBlock + tid;
+                    bool ev = false;
+                    if (loc < c.len) {
+                        const int64_t j = c.begin + loc;
+                        T rate, chi;
+                        if (photon) {
+                            const dev::ChiGamma cg = dev::chi_of<T, true>(kChiMode, v[b][0], v[b][1], v[b][2], v[b][3],
+                                                                          v[b][4], v[b][5], v[b][6], v[b][7], v[b][8]);
+                            chi = static_cast<T>(cg.chi);
+                            rate = dev::rate_bw<T>(t_bw, a.bw, chi, static_cast<T>(cg.gamma));
+                        } else {
+                            const dev::ChiGamma cg = dev::chi_of<T, false>(kChiMode, v[b][0], v[b][1], v[b][2], v[b][3],
+                                                                           v[b][4], v[b][5], v[b][6], v[b][7], v[b][8]);
+                            chi = static_cast<T>(cg.chi);
+                            rate = dev::rate_qs<T>(t_qs, a.qs, chi, static_cast<T>(cg.gamma));
+                        }
+                        const T tn = v[b][9] - rate * dt;
+                        ev = tn < T(0);
+                        if (ev) s_chi[loc] = chi;
+                        else stnt<T>(S.p[9], j, tn);
+                        if (S.flags) S.flags[j] = static_cast<uint8_t>(ev);
+                    }
+                    const unsigned long long m = __ballot(ev);
+                    if (lane == 0) emask[(it + b) * (kBlock / 64) + wave] = m;
                 }
             }
-            const unsigned long long m = __ballot(ev);
-            if (lane == 0) emask[it * (kBlock / 64) + wave] = m;
         }
         __syncthreads();
 
@@ -309,6 +347,35 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
         const int total = s_total;
         __syncthreads();
 
+        // ---------------- surrogate pass (FP32 data only): the network's
+        // sample overwrites the event's LDS chi word and its smask bit is
+        // set; events outside the trained domain or in a wave whose probe
+        // failed keep chi and use the table.  A pass of its own, so that the
+        // network's registers are not live in the event phase.
+        bool surr_on = false;
+        if constexpr (kSurr && sizeof(T) == 4) {
+            surr_on = photon ? a.use_bw_surr : a.use_qs_surr;
+            if (surr_on) {
+                const SurrogateDev& sv = photon ? a.bw_surr : a.qs_surr;
+                for (int e0 = 0; e0 < total; e0 += kBlock) {
+                    const int e = e0 + tid;
+                    const bool valid = e < total;
+                    const int le = valid ? evlist[e] : 0;
+                    const float chi = valid ? s_chi[le] : 1.f;
+                    float r = 0.5f;
+                    if (valid)
+                        r = static_cast<float>(dev::draws(a.seed, static_cast<unsigned long long>(S.id_base + c.begin + le),
+                                                          a.step, static_cast<unsigned long long>(S.species), 0ULL).u[0]);
+                    const float v = surr_wave_sample(a, sv, photon ? a.bw : a.qs, valid, chi, r, s_surr_y[wave], a.stats);
+                    const bool have = valid && !__builtin_isnan(v);
+                    if (have) s_chi[le] = v;
+                    const unsigned long long m = __ballot(have);
+                    if (lane == 0) smask[(e0 >> 6) + wave] = m;
+                }
+                __syncthreads();
+            }
+        }
+
         // ---------------- product count (photons below threshold are dropped)
         const bool thresh = !photon && a.photon_min_energy > 0.0;
         if (thresh) {
@@ -316,9 +383,11 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
                 const int e = e0 + tid;
                 const bool valid = e < total;
                 // idle lanes read a valid particle (the chunk's first) and discard it
-                const EventCtx<T> ec = load_event<T, false, kChiMode>(a, S, c.begin + (valid ? evlist[e] : 0));
+                const int le = valid ? evlist[e] : evlist[0];
+                const EventCtx<T> ec = load_event<T, false>(a, S, c.begin + le, s_chi[le]);
+                const bool have = surr_on && valid && ((smask[e >> 6] >> (e & 63)) & 1ULL);
                 T xi;
-                const T gg = qs_photon_energy<T, kSurr>(a, valid, ec, xi, s_surr_y[wave]);
+                const T gg = qs_photon_energy<T>(a, valid, have, ec, xi);
                 const bool keep = valid && gg >= static_cast<T>(a.photon_min_energy);
                 const unsigned long long m = __ballot(keep);
                 if (lane == 0) kmask[(e0 >> 6) + wave] = m;
@@ -371,12 +440,14 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
         for (int e0 = 0; e0 < total; e0 += kBlock) {
             const int e = e0 + tid;
             const bool valid = e < total;
-            const int64_t j = valid ? c.begin + evlist[e] : c.begin;
+            const int le = valid ? evlist[e] : evlist[0];   // idle lanes shadow the first event
+            const int64_t j = c.begin + le;
             const int64_t parent = S.id_base + j;
+            const bool have = surr_on && valid && ((smask[e >> 6] >> (e & 63)) & 1ULL);
             if (photon) {
-                const EventCtx<T> ec = load_event<T, true, kChiMode>(a, S, j);
+                const EventCtx<T> ec = load_event<T, true>(a, S, j, s_chi[le]);
                 bool esel;
-                const T xi = bw_xi<T, kSurr>(a, valid, static_cast<T>(ec.chi), static_cast<T>(ec.d.u[0]), esel, s_surr_y[wave]);
+                const T xi = bw_xi<T>(a, valid, have, static_cast<T>(ec.chi), static_cast<T>(ec.d.u[0]), esel);
                 if (valid) {
                     const T w = S.p[10] ? ld<T>(S.p[10], j) : T(1);
                     const T sx = xi * ec.ux, sy = xi * ec.uy, sz = xi * ec.uz;
@@ -394,9 +465,9 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
                     st<T>(S.p[9], j, static_cast<T>(__builtin_inf()));
                 }
             } else {
-                const EventCtx<T> ec = load_event<T, false, kChiMode>(a, S, j);
+                const EventCtx<T> ec = load_event<T, false>(a, S, j, s_chi[le]);
                 T xi;
-                const T gg = qs_photon_energy<T, kSurr>(a, valid, ec, xi, s_surr_y[wave]);
+                const T gg = qs_photon_energy<T>(a, valid, have, ec, xi);
                 if (valid) {
                     const T w = S.p[10] ? ld<T>(S.p[10], j) : T(1);
                     const T um = static_cast<T>(sqrt(ec.u2));
@@ -469,26 +540,30 @@ __global__ void __launch_bounds__(256) evolve_kernel(ElemArgs a) {
     }
 }
 
-template <typename T>
+// T: arithmetic and array type; S: table storage (S = Bf16 reads the BF16
+// copies with FP32 arithmetic, for precision studies).
+template <typename T, typename S>
 __global__ void __launch_bounds__(256) table_rate_kernel(TableCallArgs a) {
-    const T* lr = ln_rate_ptr<T>(a.table);
+    const S* lr;
+    if constexpr (sizeof(S) == 2) lr = reinterpret_cast<const S*>(a.table.ln_rate16);
+    else lr = ln_rate_ptr<S>(a.table);
     for (int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; j < a.n; j += int64_t(gridDim.x) * blockDim.x) {
         const T chi = ld<T>(a.a, j), g = ld<T>(a.b, j);
-        st<T>(a.out, j, a.process == QED_PROC_BW ? dev::rate_bw<T>(lr, a.table, chi, g)
-                                                 : dev::rate_qs<T>(lr, a.table, chi, g));
+        st<T>(a.out, j, a.process == QED_PROC_BW ? dev::rate_bw<T, S>(lr, a.table, chi, g)
+                                                 : dev::rate_qs<T, S>(lr, a.table, chi, g));
     }
 }
 
-template <typename T>
+template <typename T, typename S>
 __global__ void __launch_bounds__(256) table_sample_kernel(TableCallArgs a) {
     for (int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; j < a.n; j += int64_t(gridDim.x) * blockDim.x) {
         const T chi = ld<T>(a.a, j), r = ld<T>(a.b, j);
         if (a.process == QED_PROC_BW) {
             bool e;
-            st<T>(a.out, j, dev::sample_bw<T>(a.table, chi, r, e));
+            st<T>(a.out, j, dev::sample_bw<T, S>(a.table, chi, r, e));
             if (a.sel) a.sel[j] = static_cast<uint8_t>(e);
         } else {
-            st<T>(a.out, j, dev::sample_qs_lnxi<T>(a.table, chi, r));
+            st<T>(a.out, j, dev::sample_qs_lnxi<T, S>(a.table, chi, r));
         }
     }
 }
@@ -496,7 +571,7 @@ __global__ void __launch_bounds__(256) table_sample_kernel(TableCallArgs a) {
 size_t step_lds_bytes(const StepArgs& a, size_t elem) {
     const int nbw = a.bw.n_chi > 0 ? a.bw.n_chi : 0;
     const int nqs = a.qs.n_chi > 0 ? a.qs.n_chi : 0;
-    return elem * (((nbw + 1) & ~1) + ((nqs + 1) & ~1)) + sizeof(uint16_t) * kChunk;
+    return elem * (((nbw + 1) & ~1) + ((nqs + 1) & ~1)) + sizeof(uint16_t) * kChunk + elem * kChunk;
 }
 
 template <typename T, bool kSurr>
@@ -524,36 +599,48 @@ hipError_t launch_step(const StepArgs& a, int dtype, int grid, hipStream_t s) {
     return launch_step_t<float, false>(a, grid, s);
 }
 
-int step_grid_size(int dtype, bool surr, int device) {
+namespace {
+template <typename T, bool kSurr>
+int occupancy(const StepArgs& a, size_t lds) {
+    int per_cu = 0;
+    hipError_t e;
+    if (a.chi_mode == QED_CHI_COMP32)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_kernel<T, QED_CHI_COMP32, kSurr>, kBlock, lds);
+    else if (a.chi_mode == QED_CHI_FP32)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_kernel<T, QED_CHI_FP32, kSurr>, kBlock, lds);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_kernel<T, QED_CHI_FP64, kSurr>, kBlock, lds);
+    return (e == hipSuccess && per_cu > 0) ? per_cu : 1;
+}
+}  // namespace
+
+// Persistent grid: as many blocks as fit on the device at once (never more
+// than there are chunks), for the kernel variant and LDS size of this launch.
+int step_grid_size(const StepArgs& a, int dtype, int device) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
         cus = 256;
-    int per_cu = 0;
-    hipError_t e;
-    if (dtype == QED_FP64)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_kernel<double, QED_CHI_FP64, false>, kBlock,
-                                                         sizeof(double) * 2 * kMaxTableChi + 2 * kChunk);
-    else if (surr)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_kernel<float, QED_CHI_FP64, true>, kBlock,
-                                                         sizeof(float) * 2 * kMaxTableChi + 2 * kChunk);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_kernel<float, QED_CHI_FP64, false>, kBlock,
-                                                         sizeof(float) * 2 * kMaxTableChi + 2 * kChunk);
-    if (e != hipSuccess || per_cu <= 0) per_cu = 4;
+    const bool surr = a.use_bw_surr || a.use_qs_surr;
+    int per_cu;
+    if (dtype == QED_FP64) per_cu = occupancy<double, false>(a, step_lds_bytes(a, 8));
+    else if (surr) per_cu = occupancy<float, true>(a, step_lds_bytes(a, 4));
+    else per_cu = occupancy<float, false>(a, step_lds_bytes(a, 4));
     return cus * per_cu;
 }
 
 hipError_t launch_table_rate(const TableCallArgs& a, int dtype, hipStream_t s) {
     const int g = elem_grid(a.n);
-    if (dtype == QED_FP64) hipLaunchKernelGGL((table_rate_kernel<double>), dim3(g), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((table_rate_kernel<float>), dim3(g), dim3(256), 0, s, a);
+    if (dtype == QED_FP64) hipLaunchKernelGGL((table_rate_kernel<double, double>), dim3(g), dim3(256), 0, s, a);
+    else if (dtype == QED_BF16) hipLaunchKernelGGL((table_rate_kernel<float, dev::Bf16>), dim3(g), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((table_rate_kernel<float, float>), dim3(g), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_table_sample(const TableCallArgs& a, int dtype, hipStream_t s) {
     const int g = elem_grid(a.n);
-    if (dtype == QED_FP64) hipLaunchKernelGGL((table_sample_kernel<double>), dim3(g), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((table_sample_kernel<float>), dim3(g), dim3(256), 0, s, a);
+    if (dtype == QED_FP64) hipLaunchKernelGGL((table_sample_kernel<double, double>), dim3(g), dim3(256), 0, s, a);
+    else if (dtype == QED_BF16) hipLaunchKernelGGL((table_sample_kernel<float, dev::Bf16>), dim3(g), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((table_sample_kernel<float, float>), dim3(g), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

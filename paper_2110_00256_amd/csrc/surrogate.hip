@@ -46,7 +46,8 @@ constexpr unsigned long long kTrainStep = 0x5452414E494E4700ULL;   // draw strea
 // ------------------------------------------------------------ training set
 // Sample i: chi log-uniform over the trained range, u uniform over the
 // network's input domain, target from the FP64 table inverse CDF (Sec. 3.1 /
-// 3.2), weight (du/dt)^2 so that the loss measures error in CDF space (the
+// 3.2), weight (du/dy)^2 with y the sampled quantity in the network's output
+// units, so that the loss measures error in CDF space (the
 // quantity a KS distance sees).
 __device__ __forceinline__ double surr_target(const TableDev& t, int process, double chi, double u) {
     if (process == 1) {
@@ -70,10 +71,16 @@ __global__ void __launch_bounds__(256) surr_make_set(TableDev t, SurrogateDev s,
         if (s.process == 1) u = kSurrUMin + (static_cast<double>(kSurrUMaxQs) - kSurrUMin) * d.u[1];
         else u = kSurrUMin + (0.5 - kSurrUMin) * d.u[1];
         const double tgt = surr_target(t, s.process, chi, u);
+        // slope of the sampled quantity itself (QS: ln Y = target + 3 ln u;
+        // BW: the target is linear in xi), so that w (dy)^2 = (du)^2
         const double h = 1e-6 * (s.process == 1 ? fmin(u, 1.0 - u) : u) + 1e-12;
-        const double ta = surr_target(t, s.process, chi, fmax(u - h, 1e-15));
-        const double tb = surr_target(t, s.process, chi, fmin(u + h, 1.0 - 1e-15));
-        const double slope = fabs(tb - ta) / (2.0 * h);
+        const double ua = fmax(u - h, 1e-15), ub = fmin(u + h, 1.0 - 1e-15);
+        double ta = surr_target(t, s.process, chi, ua), tb = surr_target(t, s.process, chi, ub);
+        if (s.process == 1) {
+            ta += 3.0 * log(ua);
+            tb += 3.0 * log(ub);
+        }
+        const double slope = fabs(tb - ta) / (ub - ua);
         const double w = 1.0 / fmax(slope * slope, 1e-2);
         float x0, x1;
         surr_features(s, static_cast<float>(chi), static_cast<float>(u), x0, x1);
@@ -494,8 +501,8 @@ extern "C" int32_t qed_surrogate_train(qed_context* ctx, const qed_table* table,
         const double frac = static_cast<double>(it) / cfg->steps;
         const float lr = static_cast<float>(cfg->lr * (0.01 + 0.99 * 0.5 * (1.0 + std::cos(3.141592653589793 * frac))));
         hipLaunchKernelGGL(surr_update_kernel, dim3((kNParam + 256) / 256), dim3(256), 0, st, s->d_p, s->d_m, s->d_v,
-                           s->d_w2, part, n_waves, lr, static_cast<float>(1.0 - b1t), static_cast<float>(1.0 - b2t),
-                           nullptr, losses + it);
+                           s->d_w2, part, n_waves, lr, static_cast<float>(b1t), static_cast<float>(b2t), nullptr,
+                           losses + it);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);

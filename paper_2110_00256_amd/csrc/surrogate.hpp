@@ -8,7 +8,7 @@
 //
 // Input / output maps (shared by training targets and inference):
 //   x0 = (ln chi - mid) / half, mid/half of ln chi over the trained range.
-//   QS: x1 = 1 + 2 ln u / (-ln u_min); output y -> ln Y = y + 3 ln u with
+//   QS: x1 = logit(u) scaled to [-1, 1]; output y -> ln Y = y + 3 ln u with
 //       Y = 2 xi / (3 chi (1 - xi)) (the argument of the Bessel functions of
 //       Sec. 2.2; the cube term is the small-xi law P ~ xi^{1/3}), so
 //       xi = k Y / (1 + k Y), k = 3 chi / 2.
@@ -62,12 +62,18 @@ __device__ __forceinline__ float surr_ndtri_lower(float r) {
 }
 
 constexpr float kSurrUMaxQs = 1.0f - 1e-5f;   // above: the hard-photon tail goes to the table
+// logit(u) = ln u - ln(1 - u) spans [-9.21024, 11.51292] over [1e-4, 1 - 1e-5]
+constexpr float kSurrLogitMid = 1.15134f;
+constexpr float kSurrLogitInvHalf = 1.0f / 10.36158f;
 
 // Network features for (chi, u) without domain checks.
 __device__ __forceinline__ void surr_features(const SurrogateDev& s, float chi, float u, float& x0, float& x1) {
     x0 = (logf(chi) - s.mid) * s.inv_half;
     if (s.process == 1) {
-        x1 = 1.0f + 2.0f * logf(u) / 9.21034037f;   // -ln(1e-4)
+        // logit of u over [1e-4, 1 - 1e-5] -> [-1, 1]: resolves both the
+        // soft end (xi ~ u^3) and the hard tail, where ln Y grows like
+        // -ln(1 - u)
+        x1 = (logf(u) - log1pf(-u) - kSurrLogitMid) * kSurrLogitInvHalf;
     } else {
         const float r = u <= 0.5f ? u : 1.0f - u;
         x1 = 1.0f + 2.0f * surr_ndtri_lower(r) / kBwQMin;
@@ -132,7 +138,9 @@ __device__ __forceinline__ float surr_forward_wave(const SurrogateDev& s, float 
         w3[nt] = p[kOffW3 + nt * 16 + col];
     }
     const float b3 = p[kOffB3];
-#pragma unroll
+    // one 16-sample group at a time keeps the live registers of the fused
+    // step kernel low (its streaming phase needs the occupancy)
+#pragma unroll 1
     for (int q = 0; q < 4; ++q) {
         const float sx0 = __shfl(x0, q * 16 + col);
         const float sx1 = __shfl(x1, q * 16 + col);

@@ -60,12 +60,14 @@ void free_device(qed_table* t) {
     hipFree(t->d_ln_rate32);
     hipFree(t->d_cdf32);
     hipFree(t->d_cdf16);
+    hipFree(t->d_ln_rate16);
     hipSetDevice(cur);
     t->d_ln_rate64 = nullptr;
     t->d_cdf64 = nullptr;
     t->d_ln_rate32 = nullptr;
     t->d_cdf32 = nullptr;
     t->d_cdf16 = nullptr;
+    t->d_ln_rate16 = nullptr;
     t->device = -1;
 }
 
@@ -80,6 +82,7 @@ qedmi::TableDev qed_table::view() const {
     v.ln_rate32 = d_ln_rate32;
     v.cdf32 = d_cdf32;
     v.cdf16 = d_cdf16;
+    v.ln_rate16 = d_ln_rate16;
     v.n_chi = p.n_chi;
     v.n_frac = p.n_frac;
     v.chi_min = p.chi_min;
@@ -199,8 +202,11 @@ extern "C" int32_t qed_table_to_device(qed_table* t, void* stream) {
     free_device(t);
     const size_t nr = t->ln_rate.size(), nc = t->cdf.size();
     std::vector<float> r32(nr), c32(nc);
-    std::vector<uint16_t> c16(nc);
-    for (size_t i = 0; i < nr; ++i) r32[i] = static_cast<float>(t->ln_rate[i]);
+    std::vector<uint16_t> c16(nc), r16(nr);
+    for (size_t i = 0; i < nr; ++i) {
+        r32[i] = static_cast<float>(t->ln_rate[i]);
+        r16[i] = to_bf16(r32[i]);
+    }
     for (size_t i = 0; i < nc; ++i) {
         c32[i] = static_cast<float>(t->cdf[i]);
         c16[i] = to_bf16(c32[i]);
@@ -208,7 +214,7 @@ extern "C" int32_t qed_table_to_device(qed_table* t, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (hipMalloc(&t->d_ln_rate64, nr * 8) != hipSuccess || hipMalloc(&t->d_cdf64, nc * 8) != hipSuccess ||
         hipMalloc(&t->d_ln_rate32, nr * 4) != hipSuccess || hipMalloc(&t->d_cdf32, nc * 4) != hipSuccess ||
-        hipMalloc(&t->d_cdf16, nc * 2) != hipSuccess) {
+        hipMalloc(&t->d_cdf16, nc * 2) != hipSuccess || hipMalloc(&t->d_ln_rate16, nr * 2) != hipSuccess) {
         t->device = dev;
         free_device(t);
         set_error("device allocation failed");
@@ -221,6 +227,7 @@ extern "C" int32_t qed_table_to_device(qed_table* t, void* stream) {
         hipMemcpyAsync(t->d_ln_rate32, r32.data(), nr * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(t->d_cdf32, c32.data(), nc * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(t->d_cdf16, c16.data(), nc * 2, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(t->d_ln_rate16, r16.data(), nr * 2, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
         set_error("table upload failed");
         return QED_ERR_HIP;

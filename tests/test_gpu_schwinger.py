@@ -1,0 +1,121 @@
+"""Schwinger pair production on the GPU against the oracle (Sec. 2.3).
+
+Rate: FP64 arithmetic for FP64 and FP32 fields, within 1e-11 relative of the
+binary128 printed formula (the exponential exp(-pi/eps) multiplies the
+relative error of eps by pi/eps <= 745 before underflow).  Pairs: per-cell
+counts, parent ids and slots bit-exact except where the oracle's deciding
+comparison lies within 1e-9 of its boundary (the GPU's exp/log/cos may
+differ from the host's in the last bit); optical depths within 1e-12 (FP64)
+or 1e-6 (FP32)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import paper_2110_00256_amd as Q  # noqa: E402
+import qed_inputs as QI  # noqa: E402
+from oracle import oracle as O  # noqa: E402
+
+ES, C = QI.E_SCHWINGER, QI.C_LIGHT
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return Q.Context(0)
+
+
+def _fields(n, seed, scale=0.15):
+    rng = np.random.default_rng(seed)
+    f = {k: rng.normal(size=n) * scale * ES for k in ("ex", "ey", "ez")}
+    f.update({k: rng.normal(size=n) * scale * ES / C for k in ("bx", "by", "bz")})
+    # special cells: zero, pure B, crossed, pure E, parallel, weak
+    sp = [dict(ex=0, ey=0, ez=0, bx=0, by=0, bz=0), dict(ex=0, ey=0, ez=0, bx=0, by=0, bz=0.2 * ES / C),
+          dict(ex=0, ey=0.3 * ES, ez=0, bx=0, by=0, bz=0.3 * ES / C), dict(ex=0.4 * ES, ey=0, ez=0, bx=0, by=0, bz=0),
+          dict(ex=0.2 * ES, ey=0, ez=0, bx=0.1 * ES / C, by=0, bz=0), dict(ex=1e-3 * ES, ey=0, ez=0, bx=0, by=0, bz=0)]
+    for i, d in enumerate(sp):
+        for k, v in d.items():
+            f[k][i] = v
+    return f
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("n", [1, 4095, 4096, 100003])
+def test_rate_matches_oracle(ctx, dtype, n):
+    f = _fields(n, 5 + n)
+    d = {k: torch.as_tensor(v).to("cuda", dtype) for k, v in f.items()}
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    Q.schwinger_rate(ctx, Q.cells(d), out)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    ref = O.schwinger_rate_array({k: v.cpu().numpy().astype(np.float64) for k, v in d.items()})
+    both0 = (g == 0) & (ref == 0)
+    rel = np.abs(g - ref) / np.maximum(np.abs(ref), 1e-300)
+    rel[both0] = 0
+    assert np.max(rel) < 1e-11, np.max(rel)
+    if n >= 6:
+        assert g[0] == 0 and g[1] == 0 and g[2] == 0 and g[5] == 0 and g[3] > 0 and g[4] > 0
+
+
+def test_rate_empty(ctx):
+    d = {k: torch.empty(0, dtype=torch.float64, device="cuda") for k in ("ex", "ey", "ez", "bx", "by", "bz")}
+    Q.schwinger_rate(ctx, Q.cells(d), torch.empty(0, dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("dtype,tau_tol", [(torch.float64, 1e-12), (torch.float32, 1e-6)])
+@pytest.mark.parametrize("n,lam_scale", [(10000, 3.0), (70001, 0.2), (3000, 60.0)])
+def test_pairs_match_oracle(ctx, dtype, tau_tol, n, lam_scale):
+    f = _fields(n, 17 + n)
+    d = {k: torch.as_tensor(v).to("cuda", dtype) for k, v in f.items()}
+    f64 = {k: v.cpu().numpy().astype(np.float64) for k, v in d.items()}
+    rate = O.schwinger_rate_array(f64)
+    dv, dt = 1e-21, 1e-16
+    w = float(np.mean(rate) * dv * dt / lam_scale)
+    base = 1000
+    seed, step = 9, 4
+    cap = int(4 * np.sum(rate * dv * dt / w) + 1000)
+    el, po = Q.AppendBuffer(cap, dtype), Q.AppendBuffer(cap, dtype)
+    el.count.fill_(3)   # append after existing content
+    po.count.fill_(5)
+    Q.schwinger_pairs(ctx, Q.cells(d, base), dv, dt, w, seed, step, el, po)
+    torch.cuda.synchronize()
+    oel, opo = O.schwinger_pairs(f64, base, dv, dt, w, seed, step, capacity=cap)
+    ne, npo = int(el.count.item()) - 3, int(po.count.item()) - 5
+    assert ne == npo
+    gpar = el.parent[3:3 + ne].cpu().numpy()
+    assert np.array_equal(gpar, po.parent[5:5 + ne].cpu().numpy())
+    gk = np.bincount(gpar - base, minlength=n)
+    ok_ = np.bincount(oel["parent"] - base, minlength=n)
+    diff = np.nonzero(gk != ok_)[0]
+    for i in diff:
+        _, margin = O.schwinger_count(rate[i] * dv * dt / w, seed, base + i, step)
+        assert margin < 1e-9, f"cell {i}: count {gk[i]} vs oracle {ok_[i]}, margin {margin}"
+    assert len(diff) <= 2
+    if len(diff) == 0:
+        assert ne == oel.count
+        assert np.array_equal(gpar, oel["parent"])
+        for buf, off, ob in ((el, 3, oel), (po, 5, opo)):
+            t = buf.a["tau"][off:off + ne].cpu().numpy().astype(np.float64)
+            assert np.max(np.abs(t - ob["tau"]) / ob["tau"]) < tau_tol
+            assert np.all(buf.a["ux"][off:off + ne].cpu().numpy() == 0)
+            assert np.all(buf.a["w"][off:off + ne].cpu().numpy().astype(np.float64) == np.float64(np.array(w, dtype=buf.a["w"].cpu().numpy().dtype)))
+    assert ne > 0
+
+
+def test_pairs_capacity(ctx):
+    n = 5000
+    f = _fields(n, 99)
+    d = {k: torch.as_tensor(v).cuda() for k, v in f.items()}
+    rate = O.schwinger_rate_array(f)
+    dv, dt = 1e-21, 1e-16
+    w = float(np.mean(rate) * dv * dt / 2.0)
+    full = Q.AppendBuffer(8 * n, torch.float64), Q.AppendBuffer(8 * n, torch.float64)
+    Q.schwinger_pairs(ctx, Q.cells(d), dv, dt, w, 1, 0, *full)
+    need = full[0].read_count()
+    small = Q.AppendBuffer(need // 2, torch.float64), Q.AppendBuffer(need // 2, torch.float64)
+    Q.schwinger_pairs(ctx, Q.cells(d), dv, dt, w, 1, 0, *small)
+    assert small[0].read_count() == need
+    assert np.array_equal(small[0].parent.cpu().numpy(), full[0].parent[:need // 2].cpu().numpy())

@@ -100,3 +100,5 @@ def test_null_arguments_are_refused_without_launch():
     assert L.qed_read_count(None, None, None) == Q.QED_ERR_INVALID
     assert L.qed_table_to_device(None, None) == Q.QED_ERR_INVALID
     assert L.qed_context_create(0, None) == Q.QED_ERR_INVALID
+    assert L.qed_schwinger_rate(None, None, None, None) == Q.QED_ERR_INVALID
+    assert L.qed_schwinger_pairs(None, None, 1.0, 1.0, 1.0, 0, 0, None, None, None) == Q.QED_ERR_INVALID
