@@ -145,6 +145,80 @@ def cpu_baseline(pops_small, tables_params, dt, seed=1):
                        f"(FP64 C oracle, OpenMP over particles, sequential append), {wall:.1f} s")
 
 
+def fullstep(Q, torch, QI, args):
+    """4 species x 2^(log2n + 1) particles (default 2^25 each: 2^27 in all),
+    1024 lognormal tiles per species interleaved, FP32 fields of a focused
+    Gaussian pulse, dt for 1% events; one persistent launch per step."""
+    n = 1 << (args.log2n + 1)
+    dt = json.load(open(os.path.join(ROOT, "tests", "golden", "c5_dt.json")))["dt_s"]
+    log(f"fullstep: generating 4 x {n} particles and 4096 tiles")
+    pops = QI.fullstep_population(n, seed=1)
+    tiles = QI.fullstep_layout(n, 1024, seed=1)
+    ctx = Q.Context(0)
+    log("fullstep: 256x256 tables over [1e-4, 1e4]")
+    bw = Q.Table.generate(Q.BW, 1e-4, 1e4, 256, 256).to_device()
+    qs = Q.Table.generate(Q.QS, 1e-4, 1e4, 256, 256).to_device()
+    species = (Q.ELECTRON, Q.POSITRON, Q.PHOTON, Q.ION)
+    dev, sets = [], []
+    for i, (pop, sp) in enumerate(zip(pops, species)):
+        d = {k: torch.as_tensor(v).cuda() for k, v in pop.items()}
+        d["tau"] = torch.zeros(n, dtype=torch.float32, device="cuda")
+        dev.append(d)
+        sets.append(Q.particles(d, sp, id_base=i * n))
+    del pops
+    log("fullstep: training surrogates")
+    t0 = time.perf_counter()
+    sq, lq = Q.Surrogate.train(ctx, qs, Q.Surrogate.cfg(Q.QS, 1e-3, 1e3, n_samples=1 << 22, steps=20000))
+    sb, lb = Q.Surrogate.train(ctx, bw, Q.Surrogate.cfg(Q.BW, 1e-3, 1e3, n_samples=1 << 22, steps=20000))
+    train_s = time.perf_counter() - t0
+    out = {"workload": "fullstep: 4 x 2^%d particles (e-, e+, photons, ions passthrough), 4096 lognormal tiles, "
+                       "Gaussian pulse a0=500 w0=2um, FP32, dt %.3e s" % (int(np.log2(n)), dt),
+           "surrogate_train_s": train_s, "surrogate_final_loss": {"qs": lq, "bw": lb}}
+    for name, surr in (("fp32_table", (None, None)), ("fp32_surrogate", (sb, sq))):
+        for s in sets[:3]:
+            Q.init_optical_depth(ctx, s, 1)
+        counts = torch.zeros(3, dtype=torch.int64, device="cuda")
+        bufs = []
+        for i in range(3):
+            b = Q.AppendBuffer(n // 8, torch.float32)
+            b.c.count = counts.data_ptr() + 8 * i
+            b.count = counts[i:i + 1]
+            bufs.append(b)
+        stats = torch.zeros(Q.STATS_LEN, dtype=torch.int64, device="cuda")
+        desc = Q.StepDesc(sets, bw=bw, qs=qs, photons=bufs[0], electrons=bufs[1], positrons=bufs[2], tiles=tiles,
+                          stats=stats, dt=dt, seed=1, bw_surrogate=surr[0], qs_surrogate=surr[1])
+        for w in range(args.warmup):
+            counts.zero_()
+            desc.set_step(w)
+            Q.step(ctx, desc)
+        torch.cuda.synchronize()
+        stats.zero_()
+        e0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        e1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            counts.zero_()
+            desc.set_step(args.warmup + i)
+            e0[i].record()
+            Q.step(ctx, desc)
+            e1[i].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        km = float(np.mean([a.elapsed_time(b) for a, b in zip(e0, e1)]))
+        st = stats.cpu().numpy()
+        upd = int(st[Q.STAT_UPDATES])
+        qs_ev, bw_ev = int(st[Q.STAT_QS_EVENTS]), int(st[Q.STAT_BW_EVENTS])
+        by = BYTES["f32"]
+        alg = by["base"] * upd + by["qs_event"] * qs_ev + by["bw_event"] * bw_ev
+        out[name] = {"updates_per_s": upd / wall, "kernel_ms_mean": km, "event_fraction": (qs_ev + bw_ev) / upd,
+                     "achieved_gbs": alg / (km * 1e-3 * args.steps) / 1e9,
+                     "frac": alg / (km * 1e-3 * args.steps) / 1e9 / HBM_PEAK_GBS,
+                     "surrogate_batches": int(st[Q.STAT_SURR_BATCHES]),
+                     "surrogate_fallbacks": int(st[Q.STAT_SURR_FALLBACK])}
+        log(f"fullstep {name}: {out[name]}")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +230,9 @@ def main():
     ap.add_argument("--cpu-sample-log2n", type=int, default=17)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
+    ap.add_argument("--workload", choices=("cone", "fullstep"), default="cone",
+                    help="cone: the default roofline workload; fullstep: 4 species in lognormal tiles, "
+                         "Gaussian pulse, FP32 table and FP32+surrogate paths")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -174,6 +251,10 @@ def main():
         torch.cuda.synchronize()
         log(f"bench: calibration copy of {args.copy_calibration_mib} MiB done")
         del src, dst
+
+    if args.workload == "fullstep":
+        fullstep(Q, torch, QI, args)
+        return
 
     n = 1 << args.log2n
     dt = 1e-16
