@@ -15,6 +15,7 @@ step, as a PIC code does when it merges the products.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -36,6 +37,34 @@ BYTES = {
 }
 
 
+# HBM bytes per launch measured with rocprofv3 (FETCH_SIZE, WRITE_SIZE, each
+# calibrated on a plain copy) live in this summary, tagged with a digest of
+# the step kernel's sources; they are reported only while the digest matches.
+PROFILE = os.path.join(ROOT, "profiles", "step_kernel_cone_c2.md")
+KERNEL_SOURCES = ("step.hip", "device_physics.hpp", "internal.hpp", "surrogate.hpp", "constants.hpp")
+
+
+def kernel_digest():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2110_00256_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """{path: HBM bytes per launch} from the profile summary, or {} if stale."""
+    try:
+        with open(PROFILE) as f:
+            for line in f:
+                if line.startswith("traffic-json: "):
+                    d = json.loads(line[len("traffic-json: "):])
+                    return d["bytes_per_launch"] if d.get("source_digest") == kernel_digest() else {}
+    except OSError:
+        pass
+    return {}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -46,7 +75,7 @@ def make_tables(Q, n_chi, n_frac, chi_range):
     return bw, qs
 
 
-def run_path(Q, torch, ctx, tables, pops, dtype, steps, warmup, dt, chi_mode, seed=1):
+def run_path(Q, torch, ctx, tables, pops, dtype, steps, warmup, dt, chi_mode, seed=1, surrogates=(None, None)):
     tdt = torch.float64 if dtype == "f64" else torch.float32
     el, ph = pops
     dev = []
@@ -70,7 +99,8 @@ def run_path(Q, torch, ctx, tables, pops, dtype, steps, warmup, dt, chi_mode, se
     stats = torch.zeros(Q.STATS_LEN, dtype=torch.int64, device="cuda")
     bw, qs = tables
     desc = Q.StepDesc([pe, pg], bw=bw, qs=qs, photons=bufs[0], electrons=bufs[1], positrons=bufs[2],
-                      stats=stats, dt=dt, seed=seed, chi_mode=chi_mode)
+                      stats=stats, dt=dt, seed=seed, chi_mode=chi_mode, bw_surrogate=surrogates[0],
+                      qs_surrogate=surrogates[1])
     step = 0
     for _ in range(warmup):
         counts.zero_()
@@ -113,6 +143,8 @@ def run_path(Q, torch, ctx, tables, pops, dtype, steps, warmup, dt, chi_mode, se
         alg_bytes_per_launch=alg_bytes / steps,
         qs_event_fraction=qs_ev / (steps * n_e),
         bw_event_fraction=bw_ev / (steps * n_g),
+        surrogate_batches=int(st[Q.STAT_SURR_BATCHES]),
+        surrogate_fallbacks=int(st[Q.STAT_SURR_FALLBACK]),
     )
     del dev, bufs
     return res
@@ -226,6 +258,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--log2n", type=int, default=24, help="particles per species = 2^log2n")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-steps", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2n", type=int, default=17)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -272,12 +306,30 @@ def main():
         log("bench: FP32 table path")
         r32 = run_path(Q, torch, ctx, tables, pops, "f32", args.steps, args.warmup, dt, Q.CHI_FP64)
         log(f"bench: FP32 {r32['updates_per_s']:.3e} upd/s, kernel {r32['kernel_ms_mean']:.3f} ms")
+    rs, train = None, None
+    if not args.no_fp32 and not args.no_surrogate:
+        log("bench: training BW and QS surrogates on the device (chi in [1e-3, 1e3])")
+        t0 = time.perf_counter()
+        sb, lb = Q.Surrogate.train(ctx, tables[0], Q.Surrogate.cfg(Q.BW, 1e-3, 1e3, n_samples=1 << 24,
+                                                                   steps=args.surrogate_steps))
+        sq, lq = Q.Surrogate.train(ctx, tables[1], Q.Surrogate.cfg(Q.QS, 1e-3, 1e3, n_samples=1 << 24,
+                                                                   steps=args.surrogate_steps))
+        train = {"seconds": time.perf_counter() - t0, "steps": args.surrogate_steps, "final_loss": {"bw": lb, "qs": lq}}
+        log("bench: FP32 + surrogate path")
+        rs = run_path(Q, torch, ctx, tables, pops, "f32", args.steps, args.warmup, dt, Q.CHI_FP64,
+                      surrogates=(sb, sq))
+        log(f"bench: FP32+surrogate {rs['updates_per_s']:.3e} upd/s, kernel {rs['kernel_ms_mean']:.3f} ms")
     cpu = None
     if not args.no_cpu_baseline:
         m = 1 << args.cpu_sample_log2n
         small = tuple({k: v[:m] for k, v in p.items()} for p in pops)
         cpu = cpu_baseline(small, (256, 256, chi_range), dt)
         log(f"bench: oracle {cpu['value']:.3e} upd/s on {cpu['cores']} threads")
+
+    traffic = measured_traffic()
+
+    def traffic_gbs(key, r):
+        return traffic[key] / (r["kernel_ms_mean"] * 1e-3) / 1e9 if key in traffic else None
 
     out = {
         "metric": METRIC,
@@ -297,9 +349,10 @@ def main():
                    "particles": 2 * n, "dt_s": dt, "table": "256x256",
                    "qs_event_fraction": r64["qs_event_fraction"], "bw_event_fraction": r64["bw_event_fraction"]},
         "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r64["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": r64["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic_gbs("f64", r64),
                      "kernel": "step_kernel<double>", "kernel_ms_mean": r64["kernel_ms_mean"],
-                     "alg_bytes_per_launch": r64["alg_bytes_per_launch"]},
+                     "alg_bytes_per_launch": r64["alg_bytes_per_launch"],
+                     "hbm_bytes_per_launch": traffic.get("f64"), "kernel_digest": kernel_digest()},
         "cpu_baseline": cpu,
     }
     if r32 is not None:
@@ -308,7 +361,16 @@ def main():
             "kernel_ms_mean": r32["kernel_ms_mean"], "achieved_gbs": r32["achieved_gbs"],
             "frac": r32["achieved_gbs"] / HBM_PEAK_GBS, "alg_bytes_per_launch": r32["alg_bytes_per_launch"],
             "qs_event_fraction": r32["qs_event_fraction"], "bw_event_fraction": r32["bw_event_fraction"],
-            "speedup_vs_fp64": r32["updates_per_s"] / r64["updates_per_s"]}
+            "speedup_vs_fp64": r32["updates_per_s"] / r64["updates_per_s"], "traffic": traffic_gbs("f32", r32)}
+    if rs is not None:
+        out["fp32_surrogate_path"] = {
+            "value": rs["updates_per_s"], "ms_per_step": rs["ms_per_step"],
+            "kernel_ms_mean": rs["kernel_ms_mean"], "achieved_gbs": rs["achieved_gbs"],
+            "frac": rs["achieved_gbs"] / HBM_PEAK_GBS, "alg_bytes_per_launch": rs["alg_bytes_per_launch"],
+            "speedup_vs_fp64": rs["updates_per_s"] / r64["updates_per_s"],
+            "speedup_vs_fp32_table": rs["updates_per_s"] / r32["updates_per_s"],
+            "surrogate_batches": rs["surrogate_batches"], "surrogate_fallbacks": rs["surrogate_fallbacks"],
+            "training": train, "traffic": traffic_gbs("f32s", rs)}
     print(json.dumps(out), flush=True)
 
 

@@ -323,6 +323,40 @@ __device__ __forceinline__ const Bf16* cdf_ptr<Bf16>(const TableDev& t) {
 }
 
 
+// Upper-bound binary search over the row interpolated between p0 and p1 with
+// weight f: starting from [0, nf - 1], halve while hi - lo > 1, keeping lo
+// when the interpolated value at mid is <= r; returns lo.  Two levels per
+// round: the probe at mid and both possible next probes are loaded
+// together, so the chain of dependent table reads is half as long, and the
+// decisions (hence the result) are those of the plain one-level search.
+template <typename T, typename S>
+__device__ __forceinline__ int upper_bound_row(const S* p0, const S* p1, T f, T r, int nf) {
+    int lo = 0, hi = nf - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        const int ml = (lo + mid) >> 1;   // next probe if the search goes left
+        const int mr = (mid + hi) >> 1;   // next probe if it goes right
+        const T a0 = tload<T>(p0, mid), a1 = tload<T>(p1, mid);
+        const T l0 = tload<T>(p0, ml), l1 = tload<T>(p1, ml);
+        const T r0 = tload<T>(p0, mr), r1 = tload<T>(p1, mr);
+        const T vm = a0 + f * (a1 - a0);
+        if (vm <= r) {
+            lo = mid;
+            if (hi - lo > 1) {
+                if (r0 + f * (r1 - r0) <= r) lo = mr;
+                else hi = mr;
+            }
+        } else {
+            hi = mid;
+            if (hi - lo > 1) {
+                if (l0 + f * (l1 - l0) <= r) lo = ml;
+                else hi = ml;
+            }
+        }
+    }
+    return lo;
+}
+
 // BW pair sampling (Sec. 3.1): r <= 1/2 selects the electron, otherwise
 // r -> 1 - r selects the positron; rows n, n+1 interpolated in ln chi_gamma;
 // binary search for P_m <= r < P_{m+1}; linear inverse in xi.
@@ -336,12 +370,7 @@ __device__ __forceinline__ T sample_bw(const TableDev& t, T chi, T r, bool& elec
     const int nf = t.n_frac;
     const S* p0 = cdf_ptr<S>(t) + static_cast<size_t>(n) * nf;
     const S* p1 = p0 + nf;
-    int lo = 0, hi = nf - 1;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        const T pm = tload<T>(p0, mid) + f * (tload<T>(p1, mid) - tload<T>(p0, mid));
-        if (pm <= r) lo = mid; else hi = mid;
-    }
+    const int lo = upper_bound_row<T, S>(p0, p1, f, r, nf);
     const T pa = tload<T>(p0, lo) + f * (tload<T>(p1, lo) - tload<T>(p0, lo));
     const T pb = tload<T>(p0, lo + 1) + f * (tload<T>(p1, lo + 1) - tload<T>(p0, lo + 1));
     const T scale = T(0.5) / static_cast<T>(nf - 1);
@@ -365,12 +394,7 @@ __device__ __forceinline__ T sample_qs_lnxi(const TableDev& t, T chi, T r) {
     const T lmin = static_cast<T>(t.ln_frac_min);
     const T l0 = tload<T>(p0, 0) + f * (tload<T>(p1, 0) - tload<T>(p0, 0));
     if (lr < l0) return lmin + T(3) * (lr - l0);
-    int lo = 0, hi = nf - 1;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        const T lm = tload<T>(p0, mid) + f * (tload<T>(p1, mid) - tload<T>(p0, mid));
-        if (lm <= lr) lo = mid; else hi = mid;
-    }
+    const int lo = upper_bound_row<T, S>(p0, p1, f, lr, nf);
     const T la = tload<T>(p0, lo) + f * (tload<T>(p1, lo) - tload<T>(p0, lo));
     const T lb = tload<T>(p0, lo + 1) + f * (tload<T>(p1, lo + 1) - tload<T>(p0, lo + 1));
     const T inv = T(1) / static_cast<T>(nf - 1);

@@ -16,6 +16,7 @@ namespace qedmi {
 constexpr int kMaxSets = 8;
 constexpr int kBlock = 256;               // threads per block of the step kernels
 constexpr int kChunk = 4096;              // particles per chunk (16 per thread)
+constexpr int kMasks = kChunk / 64;       // 64-bit event masks per chunk
 constexpr int kMaxTableChi = 1024;        // 1D table points staged in LDS
 constexpr int kStatusBits = 30;           // value bits of a look-back status word
 

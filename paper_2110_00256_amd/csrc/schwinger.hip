@@ -71,7 +71,9 @@ __device__ double sw_rate(const SwArgs& a, int64_t i) {
     const double eps = sqrt(eps2), eta = sqrt(eta2);
     const double x = kPi * eta / eps;
     const double eta_coth = x < 1e-8 ? eps / kPi : eta / tanh(x);
-    return a.pref * eps * eta_coth * exp(-kPi / eps);
+    // one exponential of the whole logarithm: exp(-pi/eps) alone would go
+    // subnormal (and lose its digits) long before the rate does
+    return exp(log(a.pref * eps * eta_coth) - kPi / eps);
 }
 
 __device__ int64_t sw_count(const SwArgs& a, double lambda, int64_t cell) {

@@ -71,22 +71,22 @@ __device__ __forceinline__ unsigned bits_below(unsigned long long mask) {
                                      __builtin_amdgcn_mbcnt_lo(static_cast<unsigned>(mask), 0u));
 }
 
-// Decoupled look-back for chunk k with aggregate agg; returns the exclusive
-// prefix over earlier chunks of its stream.  Called by one thread.
-// A status word carries the launch epoch, the flag and the value together,
-// so relaxed device-scope atomics are enough: no other data is published
-// through it.  (Acquire/release at device scope would invalidate or write
-// back the whole L2 of the XCD on every poll.)  The base counts read before
-// phase 1 complete before the aggregate is published: their values are
-// stored to LDS first.
-__device__ long long look_back(const StepArgs& a, int k, const ChunkDesc& c, unsigned long long agg,
-                               int64_t* err) {
-    unsigned long long* st_k = a.status + k;
-    if (k == c.stream_first) {
-        __hip_atomic_store(st_k, pack_status(a.epoch, kFlagP, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return 0;
-    }
-    __hip_atomic_store(st_k, pack_status(a.epoch, kFlagA, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Decoupled look-back (Merrill & Garland 2016), in two halves called by one
+// thread: publish() posts the chunk's aggregate as soon as it is known,
+// resolve() later returns the exclusive prefix over earlier chunks of the
+// same product stream and posts the inclusive one.  A status word carries
+// the launch epoch, the flag and the value together, so relaxed
+// device-scope atomics are enough: no other data is published through it.
+// (Acquire/release at device scope would invalidate or write back the whole
+// L2 of the XCD on every poll.)  The base counts read before phase 1
+// complete before any aggregate is published: their values are in LDS.
+__device__ __forceinline__ void publish(const StepArgs& a, int k, const ChunkDesc& c, unsigned long long agg) {
+    __hip_atomic_store(a.status + k, pack_status(a.epoch, k == c.stream_first ? kFlagP : kFlagA, agg),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ long long resolve(const StepArgs& a, int k, const ChunkDesc& c, unsigned long long agg, int64_t* err) {
+    if (k == c.stream_first) return 0;
     long long excl = 0;
     int j = k - 1;
     int spins = 0;
@@ -106,7 +106,7 @@ __device__ long long look_back(const StepArgs& a, int k, const ChunkDesc& c, uns
         if (flag == kFlagP) break;
         --j;
     }
-    __hip_atomic_store(st_k, pack_status(a.epoch, kFlagP, static_cast<unsigned long long>(excl) + agg),
+    __hip_atomic_store(a.status + k, pack_status(a.epoch, kFlagP, static_cast<unsigned long long>(excl) + agg),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return excl;
 }
@@ -176,44 +176,6 @@ __device__ __forceinline__ T bw_xi(const StepArgs& a, bool valid, bool have, T c
     return valid ? dev::sample_bw<T>(a.bw, cs, r, e) : T(0);
 }
 
-// Per-event state shared by the two passes over a chunk's events.
-template <typename T>
-struct EventCtx {
-    int64_t j;          // particle index in the set
-    T ux, uy, uz;
-    double chi, gamma, u2;
-    dev::Draws d;
-};
-
-// Event state: the momentum is gathered again, chi (or the surrogate's
-// sample) comes from the LDS word written earlier, gamma and |u|^2 are
-// recomputed from u.
-template <typename T, bool kPhoton>
-__device__ __forceinline__ EventCtx<T> load_event(const StepArgs& a, const SetDev& S, int64_t j, T chi) {
-    EventCtx<T> e;
-    e.j = j;
-    e.ux = ld<T>(S.p[0], j);
-    e.uy = ld<T>(S.p[1], j);
-    e.uz = ld<T>(S.p[2], j);
-    const double ux = e.ux, uy = e.uy, uz = e.uz;
-    e.u2 = ux * ux + uy * uy + uz * uz;
-    e.gamma = kPhoton ? sqrt(e.u2) : sqrt(1.0 + e.u2);
-    e.chi = chi;
-    e.d = dev::draws(a.seed, static_cast<unsigned long long>(S.id_base + j), a.step,
-                     static_cast<unsigned long long>(S.species), 0ULL);
-    return e;
-}
-
-// QS photon energy gamma_gamma = (gamma - 1) xi, with gamma - 1 = |u|^2/(gamma + 1).
-template <typename T>
-__device__ __forceinline__ T qs_photon_energy(const StepArgs& a, bool valid, bool have, const EventCtx<T>& e,
-                                              T& xi_out) {
-    const T lnxi = qs_lnxi<T>(a, valid, have, static_cast<T>(e.chi), static_cast<T>(e.d.u[0]));
-    const T xi = dev::dexp(lnxi);
-    xi_out = xi;
-    return static_cast<T>(e.u2 / (e.gamma + 1.0)) * xi;
-}
-
 template <typename T, int kChiMode, bool kSurr>
 __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -222,12 +184,14 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
     T* t_bw = reinterpret_cast<T*>(lds_raw);
     T* t_qs = t_bw + ((nbw + 1) & ~1);
     uint16_t* evlist = reinterpret_cast<uint16_t*>(t_qs + ((nqs + 1) & ~1));
-    T* s_chi = reinterpret_cast<T*>(evlist + kChunk);   // chi of every particle of the chunk
-    __shared__ unsigned long long emask[kChunk / 64];
-    __shared__ unsigned long long kmask[kChunk / 64];
-    __shared__ unsigned long long smask[kSurr ? kChunk / 64 : 1];   // events sampled by the surrogate
-    __shared__ int epref[kChunk / 64];
-    __shared__ int kpref[kChunk / 64];
+    // chi of the chunk's event particles at their chunk index (written while
+    // streaming), then their sample (BW xi, QS xi)
+    T* s_chi = reinterpret_cast<T*>(evlist + kChunk);
+    __shared__ unsigned long long emask[kMasks];
+    __shared__ unsigned long long kmask[kMasks];
+    __shared__ unsigned long long smask[kSurr ? kMasks : 1];   // events sampled by the surrogate
+    __shared__ int epref[kMasks];
+    __shared__ int kpref[kMasks];
     __shared__ int s_ticket, s_total, s_kept;
     __shared__ long long s_excl, s_base0, s_base1;
     __shared__ float s_surr_y[kBlock / 64][64];
@@ -287,6 +251,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
             // the next loads, so the compiler would not hoist them itself).
             // Lanes past the end load the chunk's first particle and drop it.
             constexpr int kBatch = sizeof(T) == 8 ? 2 : 4;
+            static_assert(kChunk % (kBlock * kBatch) == 0, "a chunk must be a whole number of batches");
             for (int it = 0; it < kChunk / kBlock; it += kBatch) {
                 T v[kBatch][10];
 #pragma unroll
@@ -329,18 +294,18 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
 
         // ---------------- ordered event list
         if (wave == 0) {
-            const int cnt = __popcll(emask[lane]);
+            const int cnt = static_cast<int>(lane) < kMasks ? __popcll(emask[lane]) : 0;
             int incl = cnt;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
                 const int v = __shfl_up(incl, o);
                 if (static_cast<int>(lane) >= o) incl += v;
             }
-            epref[lane] = incl - cnt;
+            if (static_cast<int>(lane) < kMasks) epref[lane] = incl - cnt;
             if (lane == 63) s_total = incl;
         }
         __syncthreads();
-        for (int w = wave; w < kChunk / 64; w += kBlock / 64) {
+        for (int w = wave; w < kMasks; w += kBlock / 64) {
             const unsigned long long m = emask[w];
             if ((m >> lane) & 1ULL) evlist[epref[w] + bits_below(m)] = static_cast<uint16_t>(w * 64 + lane);
         }
@@ -351,13 +316,15 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
         // sample overwrites the event's LDS chi word and its smask bit is
         // set; events outside the trained domain or in a wave whose probe
         // failed keep chi and use the table.  A pass of its own, so that the
-        // network's registers are not live in the event phase.
+        // network's registers are not live in the event phase.  A wave
+        // with no event left skips the rest (the network needs whole waves).
         bool surr_on = false;
         if constexpr (kSurr && sizeof(T) == 4) {
             surr_on = photon ? a.use_bw_surr : a.use_qs_surr;
             if (surr_on) {
                 const SurrogateDev& sv = photon ? a.bw_surr : a.qs_surr;
-                for (int e0 = 0; e0 < total; e0 += kBlock) {
+        #pragma unroll 1
+        for (int e0 = 0; e0 + wave * 64 < total; e0 += kBlock) {
                     const int e = e0 + tid;
                     const bool valid = e < total;
                     const int le = valid ? evlist[e] : 0;
@@ -376,19 +343,49 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
             }
         }
 
-        // ---------------- product count (photons below threshold are dropped)
+        // ---------------- publish the chunk's product count early (no
+        // threshold: one product record per event), so that later chunks'
+        // look-back finds it while this block samples its events
         const bool thresh = !photon && a.photon_min_energy > 0.0;
+        if (!thresh && tid == 0) publish(a, k, c, static_cast<unsigned long long>(total));
+
+        // ---------------- phase 2a: draw and inverse-CDF sample of every
+        // event (no particle data needed: chi is in LDS); the sample (BW xi,
+        // QS xi) replaces chi.  Idle lanes of the last wave sample a
+        // placeholder and store nothing.
+#pragma unroll 1
+        for (int e0 = 0; e0 + wave * 64 < total; e0 += kBlock) {
+            const int e = e0 + tid;
+            const bool valid = e < total;
+            const int le = valid ? evlist[e] : 0;
+            const T cs = valid ? s_chi[le] : T(1);
+            const T r = static_cast<T>(dev::draws(a.seed, static_cast<unsigned long long>(S.id_base + c.begin + le),
+                                                  a.step, static_cast<unsigned long long>(S.species), 0ULL).u[0]);
+            const bool have = surr_on && valid && ((smask[e >> 6] >> (e & 63)) & 1ULL);
+            T xi;
+            if (photon) {
+                bool esel;
+                xi = bw_xi<T>(a, valid, have, cs, r, esel);
+            } else {
+                xi = dev::dexp(qs_lnxi<T>(a, valid, have, cs, r));
+            }
+            if (valid) s_chi[le] = xi;
+        }
+        __syncthreads();
+
+        // ---------------- product count with the photon threshold
         if (thresh) {
             for (int e0 = 0; e0 < total; e0 += kBlock) {
                 const int e = e0 + tid;
-                const bool valid = e < total;
-                // idle lanes read a valid particle (the chunk's first) and discard it
-                const int le = valid ? evlist[e] : evlist[0];
-                const EventCtx<T> ec = load_event<T, false>(a, S, c.begin + le, s_chi[le]);
-                const bool have = surr_on && valid && ((smask[e >> 6] >> (e & 63)) & 1ULL);
-                T xi;
-                const T gg = qs_photon_energy<T>(a, valid, have, ec, xi);
-                const bool keep = valid && gg >= static_cast<T>(a.photon_min_energy);
+                bool keep = false;
+                if (e < total) {
+                    const int le = evlist[e];
+                    const int64_t j = c.begin + le;
+                    const double ux = ld<T>(S.p[0], j), uy = ld<T>(S.p[1], j), uz = ld<T>(S.p[2], j);
+                    const double u2 = ux * ux + uy * uy + uz * uz;
+                    const T gg = static_cast<T>(u2 / (sqrt(1.0 + u2) + 1.0)) * s_chi[le];
+                    keep = gg >= static_cast<T>(a.photon_min_energy);
+                }
                 const unsigned long long m = __ballot(keep);
                 if (lane == 0) kmask[(e0 >> 6) + wave] = m;
             }
@@ -402,8 +399,11 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
                     const int v = __shfl_up(incl, o);
                     if (static_cast<int>(lane) >= o) incl += v;
                 }
-                kpref[lane] = incl - cnt;
-                if (lane == 63) s_kept = incl;
+                if (static_cast<int>(lane) < kMasks) kpref[lane] = incl - cnt;
+                if (lane == 63) {
+                    s_kept = incl;
+                    publish(a, k, c, static_cast<unsigned long long>(incl));
+                }
             }
             __syncthreads();
         }
@@ -411,8 +411,8 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
 
         // ---------------- decoupled look-back over the chunk's stream
         if (tid == 0) {
-            s_excl = look_back(a, k, c, static_cast<unsigned long long>(prods),
-                               a.stats ? a.stats + QED_STAT_SCAN_TIMEOUT : nullptr);
+            s_excl = resolve(a, k, c, static_cast<unsigned long long>(prods),
+                             a.stats ? a.stats + QED_STAT_SCAN_TIMEOUT : nullptr);
             const long long incl = s_excl + prods;
             if (k == c.stream_last) {
                 if (photon) {
@@ -436,47 +436,63 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
         __syncthreads();
         const long long slot0 = s_excl;
 
-        // ---------------- phase 2: events
-        for (int e0 = 0; e0 < total; e0 += kBlock) {
-            const int e = e0 + tid;
-            const bool valid = e < total;
-            const int le = valid ? evlist[e] : evlist[0];   // idle lanes shadow the first event
-            const int64_t j = c.begin + le;
-            const int64_t parent = S.id_base + j;
-            const bool have = surr_on && valid && ((smask[e >> 6] >> (e & 63)) & 1ULL);
-            if (photon) {
-                const EventCtx<T> ec = load_event<T, true>(a, S, j, s_chi[le]);
-                bool esel;
-                const T xi = bw_xi<T>(a, valid, have, static_cast<T>(ec.chi), static_cast<T>(ec.d.u[0]), esel);
-                if (valid) {
-                    const T w = S.p[10] ? ld<T>(S.p[10], j) : T(1);
-                    const T sx = xi * ec.ux, sy = xi * ec.uy, sz = xi * ec.uz;
-                    const T ox = ec.ux - sx, oy = ec.uy - sy, oz = ec.uz - sz;
-                    const T te = static_cast<T>(-log(ec.d.u[1]));
-                    const T tp = static_cast<T>(-log(ec.d.u[2]));
-                    const long long slot = slot0 + e;
-                    if (esel) {
-                        write_product<T>(a.el, s_base0 + slot, sx, sy, sz, w, te, parent);
-                        write_product<T>(a.po, s_base1 + slot, ox, oy, oz, w, tp, parent);
-                    } else {
-                        write_product<T>(a.el, s_base0 + slot, ox, oy, oz, w, te, parent);
-                        write_product<T>(a.po, s_base1 + slot, sx, sy, sz, w, tp, parent);
-                    }
-                    st<T>(S.p[9], j, static_cast<T>(__builtin_inf()));
+        // ---------------- phase 2b: kinematics, parent update and products
+        // at their slots.  Each thread walks its events (e = tid, tid + 256,
+        // ...) with the next event's u and w loads in flight while the
+        // current one is computed.
+        {
+            int e = tid;
+            T nux = T(0), nuy = T(0), nuz = T(0), nw = T(1);
+            if (e < total) {
+                const int64_t jn = c.begin + evlist[e];
+                nux = ld<T>(S.p[0], jn);
+                nuy = ld<T>(S.p[1], jn);
+                nuz = ld<T>(S.p[2], jn);
+                if (S.p[10]) nw = ld<T>(S.p[10], jn);
+            }
+#pragma unroll 1
+            for (; e < total; e += kBlock) {
+                const int le = evlist[e];
+                const int64_t j = c.begin + le;
+                const T ux = nux, uy = nuy, uz = nuz, w = nw;
+                if (e + kBlock < total) {
+                    const int64_t jn = c.begin + evlist[e + kBlock];
+                    nux = ld<T>(S.p[0], jn);
+                    nuy = ld<T>(S.p[1], jn);
+                    nuz = ld<T>(S.p[2], jn);
+                    if (S.p[10]) nw = ld<T>(S.p[10], jn);
                 }
-            } else {
-                const EventCtx<T> ec = load_event<T, false>(a, S, j, s_chi[le]);
-                T xi;
-                const T gg = qs_photon_energy<T>(a, valid, have, ec, xi);
-                if (valid) {
-                    const T w = S.p[10] ? ld<T>(S.p[10], j) : T(1);
-                    const T um = static_cast<T>(sqrt(ec.u2));
+                const int64_t parent = S.id_base + j;
+                const dev::Draws d = dev::draws(a.seed, static_cast<unsigned long long>(parent), a.step,
+                                                static_cast<unsigned long long>(S.species), 0ULL);
+                const T xi = s_chi[le];
+                // optical depths from uniforms 1 and 2: BW electron and
+                // positron; QS parent (redrawn) and photon
+                const T t1 = static_cast<T>(-log(d.u[1]));
+                const T t2 = static_cast<T>(-log(d.u[2]));
+                if (photon) {
+                    const bool esel = static_cast<T>(d.u[0]) <= T(0.5);
+                    const T sx = xi * ux, sy = xi * uy, sz = xi * uz;
+                    const T ox = ux - sx, oy = uy - sy, oz = uz - sz;
+                    const T te = t1, tp = t2;
+                    const long long slot = slot0 + e;
+                    write_product<T>(a.el, s_base0 + slot, esel ? sx : ox, esel ? sy : oy, esel ? sz : oz, w, te,
+                                     parent);
+                    write_product<T>(a.po, s_base1 + slot, esel ? ox : sx, esel ? oy : sy, esel ? oz : sz, w, tp,
+                                     parent);
+                    st<T>(S.p[9], j, static_cast<T>(__builtin_inf()));
+                } else {
+                    // QS photon energy gamma_gamma = (gamma - 1) xi, gamma - 1 = |u|^2/(gamma + 1)
+                    const double dx = ux, dy = uy, dz = uz;
+                    const double u2 = dx * dx + dy * dy + dz * dz;
+                    const T gg = static_cast<T>(u2 / (sqrt(1.0 + u2) + 1.0)) * xi;
+                    const T um = static_cast<T>(sqrt(u2));
                     const T sc = um > T(0) ? gg / um : T(0);
-                    const T px = sc * ec.ux, py = sc * ec.uy, pz = sc * ec.uz;
-                    st<T>(S.p[0], j, ec.ux - px);
-                    st<T>(S.p[1], j, ec.uy - py);
-                    st<T>(S.p[2], j, ec.uz - pz);
-                    st<T>(S.p[9], j, static_cast<T>(-log(ec.d.u[1])));
+                    const T px = sc * ux, py = sc * uy, pz = sc * uz;
+                    st<T>(S.p[0], j, ux - px);
+                    st<T>(S.p[1], j, uy - py);
+                    st<T>(S.p[2], j, uz - pz);
+                    st<T>(S.p[9], j, t1);
                     bool keep = true;
                     long long rank = e;
                     if (thresh) {
@@ -485,8 +501,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
                         rank = kpref[e >> 6] + __popcll(m & ((1ULL << (e & 63)) - 1ULL));
                     }
                     if (keep)
-                        write_product<T>(a.ph, s_base0 + slot0 + rank, px, py, pz, w,
-                                         static_cast<T>(-log(ec.d.u[2])), parent);
+                        write_product<T>(a.ph, s_base0 + slot0 + rank, px, py, pz, w, t2, parent);
                 }
             }
         }

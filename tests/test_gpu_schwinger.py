@@ -1,8 +1,9 @@
 """Schwinger pair production on the GPU against the oracle (Sec. 2.3).
 
-Rate: FP64 arithmetic for FP64 and FP32 fields, within 1e-11 relative of the
-binary128 printed formula (the exponential exp(-pi/eps) multiplies the
-relative error of eps by pi/eps <= 745 before underflow).  Pairs: per-cell
+Rate: FP64 arithmetic for FP64 and FP32 fields, against the binary128 printed
+formula wherever the rate is a normal double, within the bound the
+arithmetic gives: the invariants' rounding relative to hypot(F, G), times
+1 + pi/eps (<= 745 before underflow) from the exponential.  Pairs: per-cell
 counts, parent ids and slots bit-exact except where the oracle's deciding
 comparison lies within 1e-9 of its boundary (the GPU's exp/log/cos may
 differ from the host's in the last bit); optical depths within 1e-12 (FP64)
@@ -36,7 +37,7 @@ def _fields(n, seed, scale=0.15):
     sp = [dict(ex=0, ey=0, ez=0, bx=0, by=0, bz=0), dict(ex=0, ey=0, ez=0, bx=0, by=0, bz=0.2 * ES / C),
           dict(ex=0, ey=0.3 * ES, ez=0, bx=0, by=0, bz=0.3 * ES / C), dict(ex=0.4 * ES, ey=0, ez=0, bx=0, by=0, bz=0),
           dict(ex=0.2 * ES, ey=0, ez=0, bx=0.1 * ES / C, by=0, bz=0), dict(ex=1e-3 * ES, ey=0, ez=0, bx=0, by=0, bz=0)]
-    for i, d in enumerate(sp):
+    for i, d in enumerate(sp[:n]):
         for k, v in d.items():
             f[k][i] = v
     return f
@@ -52,10 +53,25 @@ def test_rate_matches_oracle(ctx, dtype, n):
     torch.cuda.synchronize()
     g = out.cpu().numpy()
     ref = O.schwinger_rate_array({k: v.cpu().numpy().astype(np.float64) for k, v in d.items()})
-    both0 = (g == 0) & (ref == 0)
-    rel = np.abs(g - ref) / np.maximum(np.abs(ref), 1e-300)
-    rel[both0] = 0
-    assert np.max(rel) < 1e-11, np.max(rel)
+    # Bound from the arithmetic: the invariants f = (e^2 - b^2)/2, g = e.b
+    # (fields over E_s) carry an absolute rounding of ~u (e^2 + b^2), so eps
+    # has a relative error ~u (e^2 + b^2)/s, s = hypot(f, g), and the rate
+    # multiplies it by 1 + pi/eps.
+    f64 = {k: v.cpu().numpy().astype(np.float64) for k, v in d.items()}
+    e = np.stack([f64[k] for k in ("ex", "ey", "ez")]) / ES
+    b = np.stack([f64[k] for k in ("bx", "by", "bz")]) * (C / ES)
+    e2, b2, gg = (e * e).sum(0), (b * b).sum(0), (e * b).sum(0)
+    ff = 0.5 * (e2 - b2)
+    sh = np.hypot(ff, gg)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        eps = np.sqrt(np.where(ff >= 0, sh + ff, gg * gg / (sh - ff)))
+        tol = 32 * 2.0 ** -53 * (1 + np.pi / eps) * (e2 + b2) / sh + 1e-14
+    # below ~1e-290 m^-3 s^-1 (no pair in any volume or time) the doubles are
+    # subnormal or zero and carry few digits: only the size is checked there
+    normal = ref > 1e-290
+    rel = np.abs(g[normal] - ref[normal]) / ref[normal]
+    assert np.all(rel <= tol[normal]), np.max(rel / tol[normal])
+    assert np.all(g[~normal] < 1e-280)
     if n >= 6:
         assert g[0] == 0 and g[1] == 0 and g[2] == 0 and g[5] == 0 and g[3] > 0 and g[4] > 0
 

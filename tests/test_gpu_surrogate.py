@@ -96,11 +96,29 @@ def _ks_paired(a, b):
     return float(np.max(np.abs(np.searchsorted(sa, g, "right") - np.searchsorted(sb, g, "right")) / len(a)))
 
 
+@pytest.fixture(scope="module")
+def tables512():
+    """The 512 x 512 tables the surrogate is fitted to (chi over [1e-4, 1e4])."""
+    return (Q.Table.generate(Q.BW, RANGE[0], RANGE[1], 512, 512).to_device(),
+            Q.Table.generate(Q.QS, RANGE[0], RANGE[1], 512, 512).to_device())
+
+
+@pytest.fixture(scope="module")
+def trained(ctx, tables512):
+    """Both surrogates trained on 2^24 samples, 40000 Adam steps of 16384."""
+    out = {}
+    for proc in (Q.BW, Q.QS):
+        table = tables512[0] if proc == Q.BW else tables512[1]
+        cfg = Q.Surrogate.cfg(proc, 1e-3, 1e3, n_samples=1 << 24, batch=16384, steps=40000, lr=3e-3,
+                              probe_tol=1.0)
+        out[proc] = Q.Surrogate.train(ctx, table, cfg)
+    return out
+
+
 @pytest.mark.parametrize("proc", [Q.QS, Q.BW])
-def test_train_ks_fallback(ctx, tables, proc):
-    table = tables[0] if proc == Q.BW else tables[1]
-    cfg = Q.Surrogate.cfg(proc, 1e-3, 1e3, n_samples=1 << 22, batch=16384, steps=8000, lr=3e-3, probe_tol=1.0)
-    s, loss = Q.Surrogate.train(ctx, table, cfg)
+def test_train_ks_fallback(ctx, tables512, trained, proc):
+    table = tables512[0] if proc == Q.BW else tables512[1]
+    s, loss = trained[proc]
     print(f"process {proc}: final weighted loss {loss:.3e}")
     assert np.isfinite(loss)
     n = 1 << 20
@@ -120,7 +138,9 @@ def test_train_ks_fallback(ctx, tables, proc):
         ks = _ks_paired(out_s.cpu().numpy(), out_t.cpu().numpy())
         kss.append(ks)
         print(f"  chi={chi:g}: KS(surrogate, table) = {ks:.2e}")
-    assert max(kss) < 0.05
+    # measured on MI355X: QS <= 1.8e-3, BW <= 3.4e-3 (paired KS noise with
+    # 2^20 samples ~ 1e-4); the bar leaves room for training-order effects
+    assert max(kss) < 5e-3
     # outside the trained range the surrogate is the table, bit for bit
     chi = np.exp(rng.uniform(np.log(2e3), np.log(9e3), 10000)).astype(np.float32)
     u = rng.random(10000).astype(np.float32)
@@ -184,3 +204,37 @@ def test_step_with_surrogate_probe_and_counts(ctx, tables):
     ks = _ks_paired(np.log(e_s), np.log(e_t))
     print(f"photon energy KS (surrogate vs table, same draws) {ks:.2e}")
     assert ks < 0.1
+
+
+def test_gain_over_table(ctx, tables512, trained):
+    """What the network buys over the table: sampling time for 2^24 events
+    with chi log-uniform over the trained range plus 2^16 out-of-range
+    events (which fall back to the table), both kernels timed with HIP
+    events on the launch stream; the fallback events match the table bit for
+    bit."""
+    n_in, n_out = 1 << 24, 1 << 16
+    for proc in (Q.QS, Q.BW):
+        table = tables512[0] if proc == Q.BW else tables512[1]
+        s, _ = trained[proc]
+        chi = np.concatenate([QI.loguniform_chi(n_in, 3, 1e-3, 1e3), QI.loguniform_chi(n_out, 4, 2e3, 9e3)])
+        u = QI.uniforms(n_in + n_out, 3, stream=proc)
+        dc = torch.as_tensor(chi.astype(np.float32)).cuda()
+        du = torch.as_tensor(u.astype(np.float32)).cuda()
+        a, b = torch.empty_like(dc), torch.empty_like(dc)
+        times = {}
+        for name, fn in (("table", lambda: Q.table_sample(table, dc, du, b)), ("surrogate", lambda: s.sample(dc, du, a))):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(10):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            times[name] = e0.elapsed_time(e1) / 10
+        np.testing.assert_array_equal(a[n_in:].cpu().numpy(), b[n_in:].cpu().numpy())
+        tp = table.host_data()[0]
+        print(f"process {proc}: table {times['table']:.3f} ms, surrogate {times['surrogate']:.3f} ms "
+              f"for {n_in + n_out} events (gain x{times['table'] / times['surrogate']:.2f}); "
+              f"table {4 * tp.n_chi * (tp.n_frac + 1)} B in FP32, network {4 * 4417 + 2 * 4096} B")
+        assert times["surrogate"] > 0 and times["table"] > 0
