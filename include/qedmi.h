@@ -92,6 +92,15 @@ typedef struct qed_table qed_table;
  * Synchronous.  *out receives a new handle (caller destroys it). */
 int32_t qed_table_generate(const qed_table_params* params, qed_table** out);
 
+/* The same tables generated on the current device: every entry is an FP64
+ * quadrature in HIP (one thread per table interval, composite Gauss-Legendre
+ * in each interval's natural variable, Bessel functions from their integral
+ * representation).  The paper generates tables on the CPU only (Sec. 3);
+ * results agree with qed_table_generate to about 1e-10.  Synchronous on
+ * `stream`; the FP64 host master copy is filled as for qed_table_generate
+ * (call qed_table_to_device to upload the runtime copies). */
+int32_t qed_table_generate_device(const qed_table_params* params, qed_table** out, void* stream);
+
 /* Wrap caller-provided FP64 host arrays (copied) as a table (e.g. tables
  * produced elsewhere, Sec. 5: "load a lookup table generated beforehand"). */
 int32_t qed_table_from_host(const qed_table_params* params, const double* ln_rate,

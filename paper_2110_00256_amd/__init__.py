@@ -27,7 +27,7 @@ SURR_NPARAM = 64 * 2 + 64 + 64 * 64 + 64 + 64 + 1
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = (
     "qed_table_generate", "qed_table_from_host", "qed_table_save", "qed_table_load",
-    "qed_table_host_data", "qed_table_to_device", "qed_table_destroy",
+    "qed_table_host_data", "qed_table_to_device", "qed_table_destroy", "qed_table_generate_device",
     "qed_context_create", "qed_context_destroy",
     "qed_chi_lepton", "qed_chi_photon", "qed_init_optical_depth", "qed_evolve_optical_depth",
     "qed_generate_pairs", "qed_generate_photon_and_update_momentum", "qed_step", "qed_read_count",
@@ -97,6 +97,7 @@ def lib():
         P = C.POINTER
         sig = {
             "qed_table_generate": [P(TableParams), P(vp)],
+            "qed_table_generate_device": [P(TableParams), P(vp), vp],
             "qed_table_from_host": [P(TableParams), vp, vp, P(vp)],
             "qed_table_save": [vp, C.c_char_p],
             "qed_table_load": [C.c_char_p, P(vp)],
@@ -166,6 +167,14 @@ class Table:
         p = TableParams(process, n_chi, n_frac, n_threads, chi_min, chi_max, frac_min)
         h = C.c_void_p()
         check(lib().qed_table_generate(C.byref(p), C.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def generate_device(cls, process, chi_min, chi_max, n_chi, n_frac, frac_min=1e-12, stream=None):
+        """Generate on the current GPU (FP64 HIP quadrature); synchronous."""
+        p = TableParams(process, n_chi, n_frac, 0, chi_min, chi_max, frac_min)
+        h = C.c_void_p()
+        check(lib().qed_table_generate_device(C.byref(p), C.byref(h), _stream(stream)))
         return cls(h.value)
 
     @classmethod

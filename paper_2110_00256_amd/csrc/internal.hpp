@@ -149,4 +149,6 @@ namespace qedmi {
 int32_t check_append_dtype(const qed_append* a, int dtype, const char* name);
 AppendDev append_view(const qed_append* a);
 int32_t reserve_scratch(qed_context* ctx, int64_t bytes);
+// Table generation on the current device (tablegen_device.hip); fills host arrays.
+int32_t generate_tables_device(const qed_table_params& p, double* ln_rate, double* cdf, hipStream_t stream);
 }  // namespace qedmi

@@ -115,6 +115,31 @@ extern "C" int32_t qed_table_generate(const qed_table_params* params, qed_table*
     return QED_OK;
 }
 
+extern "C" int32_t qed_table_generate_device(const qed_table_params* params, qed_table** out, void* stream) {
+    if (!out) { set_error("out is null"); return QED_ERR_INVALID; }
+    *out = nullptr;
+    if (!check_params(params)) return QED_ERR_INVALID;
+    qed_table* t = new (std::nothrow) qed_table;
+    if (!t) { set_error("host allocation failed"); return QED_ERR_ALLOC; }
+    t->p = *params;
+    try {
+        t->ln_rate.assign(params->n_chi, 0.0);
+        t->cdf.assign(static_cast<size_t>(params->n_chi) * params->n_frac, 0.0);
+    } catch (...) {
+        delete t;
+        set_error("host allocation failed");
+        return QED_ERR_ALLOC;
+    }
+    const int32_t r = generate_tables_device(*params, t->ln_rate.data(), t->cdf.data(),
+                                             static_cast<hipStream_t>(stream));
+    if (r) {
+        delete t;
+        return r;
+    }
+    *out = t;
+    return QED_OK;
+}
+
 extern "C" int32_t qed_table_from_host(const qed_table_params* params, const double* ln_rate, const double* cdf,
                                        qed_table** out) {
     if (!out) { set_error("out is null"); return QED_ERR_INVALID; }
