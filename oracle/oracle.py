@@ -46,6 +46,11 @@ class _Particles(C.Structure):
                [("n", C.c_int64), ("id_base", C.c_int64), ("species", C.c_int32)]
 
 
+class _Field(C.Structure):
+    _fields_ = [("kind", C.c_int), ("dir", C.c_int), ("e0", C.c_double * 3), ("b0", C.c_double * 3),
+                ("amp", C.c_double), ("lam", C.c_double), ("phase", C.c_double)]
+
+
 class _Append(C.Structure):
     _fields_ = [(k, _dp) for k in ("ux", "uy", "uz", "w", "tau")] + \
                [("parent", _i64p), ("capacity", C.c_int64), ("count", C.c_int64)]
@@ -108,6 +113,7 @@ def lib():
         L.orc_schwinger_pairs.argtypes = [C.c_int64] + [_dp] * 6 + [C.c_int64, d, d, d, C.c_uint64, C.c_uint64,
                                                                  C.POINTER(_Append), C.POINTER(_Append)]
         L.orc_schwinger_pairs.restype = C.c_int64
+        L.orc_push.argtypes = [C.POINTER(_Particles), _dp, _dp, _dp, C.POINTER(_Field), d, d]
         _lib = L
     return _lib
 
@@ -420,3 +426,19 @@ def schwinger_pairs(cells: dict, cell_id_base, dv, dt, weight, seed, step, capac
     lib().orc_schwinger_pairs(len(cols[0]), *[_ptr(c) for c in cols], cell_id_base, dv, dt, weight, seed, step,
                               el.cstruct, po.cstruct)
     return el, po
+
+
+# ---------------------------------------------------------------- push
+def uniform_field(e0=(0.0, 0.0, 0.0), b0=(0.0, 0.0, 0.0)):
+    return _Field(0, 1, (C.c_double * 3)(*e0), (C.c_double * 3)(*b0), 0.0, 0.0, 0.0)
+
+
+def cp_wave(amplitude, wavelength, direction=1, phase=0.0):
+    return _Field(1, direction, (C.c_double * 3)(), (C.c_double * 3)(), amplitude, wavelength, phase)
+
+
+def push(p: Particles, x, y, z, field, t, dt):
+    """Boris push of p (in place) and of the positions x, y, z (float64 arrays)."""
+    for a in (x, y, z):
+        assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    lib().orc_push(p.cstruct, _ptr(x), _ptr(y), _ptr(z), C.byref(field), float(t), float(dt))

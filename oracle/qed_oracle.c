@@ -990,3 +990,69 @@ int64_t orc_schwinger_pairs(int64_t n, const double* ex, const double* ey, const
     po->count = total;
     return total;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Particle push in prescribed fields (the Sec. 5.1 benchmark geometries:   */
+/* a static B perpendicular to the electrons; a circularly polarised plane  */
+/* wave).  Leptons by the relativistic Boris scheme (Boris 1970): half      */
+/* electric kick, rotation about B by the angle 2 atan(q B dt/(2 m gamma)), */
+/* half kick; positions advanced with the new velocity.  Photons move at c. */
+/* After the move the fields at the new position and time are stored in the */
+/* particle, as the QED step reads them.                                    */
+/*   kind 0: uniform E0, B0.  kind 1: CP wave along dir * x with amplitude  */
+/*   A: E = A (0, cos ph, sin ph), B = (dir x_hat) x E / c,                 */
+/*   ph = 2 pi (dir x - c t)/lambda + phase.                                */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int kind, dir;
+    double e0[3], b0[3];
+    double amp, lambda, phase;
+} orc_field;
+
+static void orc_field_at(const orc_field* f, double x, double t, double e[3], double b[3]) {
+    if (f->kind == 0) {
+        for (int k = 0; k < 3; ++k) { e[k] = f->e0[k]; b[k] = f->b0[k]; }
+        return;
+    }
+    double ph = 2.0 * M_PI / f->lambda * (f->dir * x - ORC_C * t) + f->phase;
+    e[0] = 0.0; e[1] = f->amp * cos(ph); e[2] = f->amp * sin(ph);
+    b[0] = 0.0; b[1] = -f->dir * e[2] / ORC_C; b[2] = f->dir * e[1] / ORC_C;
+}
+
+void orc_push(orc_particles* p, double* x, double* y, double* z, const orc_field* f, double t, double dt) {
+    double qm = p->species == 0 ? -ORC_QE / ORC_ME : (p->species == 1 ? ORC_QE / ORC_ME : 0.0);
+    for (int64_t i = 0; i < p->n; ++i) {
+        double u[3] = {p->ux[i], p->uy[i], p->uz[i]};
+        double r[3] = {x[i], y[i], z[i]};
+        if (qm != 0.0) {
+            double e[3], b[3];
+            orc_field_at(f, r[0], t, e, b);
+            double kick = qm * dt / (2.0 * ORC_C);
+            double um[3];
+            for (int k = 0; k < 3; ++k) um[k] = u[k] + kick * e[k];
+            double gm = sqrt(1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+            double tv[3];
+            for (int k = 0; k < 3; ++k) tv[k] = qm * dt / (2.0 * gm) * b[k];
+            double t2 = tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2];
+            double sv[3];
+            for (int k = 0; k < 3; ++k) sv[k] = 2.0 * tv[k] / (1.0 + t2);
+            double w[3] = {um[0] + (um[1] * tv[2] - um[2] * tv[1]), um[1] + (um[2] * tv[0] - um[0] * tv[2]),
+                           um[2] + (um[0] * tv[1] - um[1] * tv[0])};
+            double up[3] = {um[0] + (w[1] * sv[2] - w[2] * sv[1]), um[1] + (w[2] * sv[0] - w[0] * sv[2]),
+                            um[2] + (w[0] * sv[1] - w[1] * sv[0])};
+            for (int k = 0; k < 3; ++k) u[k] = up[k] + kick * e[k];
+            double g = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            for (int k = 0; k < 3; ++k) r[k] += ORC_C * u[k] / g * dt;
+        } else {
+            double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            if (um > 0.0)
+                for (int k = 0; k < 3; ++k) r[k] += ORC_C * u[k] / um * dt;
+        }
+        double e[3], b[3];
+        orc_field_at(f, r[0], t + dt, e, b);
+        p->ux[i] = u[0]; p->uy[i] = u[1]; p->uz[i] = u[2];
+        p->ex[i] = e[0]; p->ey[i] = e[1]; p->ez[i] = e[2];
+        p->bx[i] = b[0]; p->by[i] = b[1]; p->bz[i] = b[2];
+        x[i] = r[0]; y[i] = r[1]; z[i] = r[2];
+    }
+}
