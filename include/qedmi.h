@@ -276,8 +276,10 @@ int32_t qed_read_count(const qed_append* a, int64_t* host_count, void* stream);
  * the sampled fraction (ln xi for QS; a scaled xi for BW), trained on
  * samples of the table inverse CDF (Sec. 3.1 / 3.2 sampling) by the
  * library's own BF16-MFMA forward/backward kernels and Adam.  Outside its
- * trained chi range, or when a per-batch probe against the table exceeds
- * `probe_tol`, sampling falls back to the table. */
+ * trained chi range, or when a probe against the table exceeds
+ * `probe_tol`, sampling falls back to the table: in the fused step one wave
+ * batch of 64 events in `probe_every` is probed, and a wave whose probe
+ * fails keeps the table for the rest of its chunk. */
 typedef struct {
     int32_t process;        /* qed_process of the table it learns         */
     int32_t n_samples;      /* training set size (e.g. 1 << 24)            */
@@ -287,6 +289,9 @@ typedef struct {
     float probe_tol;        /* allowed |delta| of the output per probe     */
     double chi_lo, chi_hi;  /* trained chi range (inside the table range)  */
     uint64_t seed;
+    int32_t probe_every;    /* in the fused step, probe one wave batch in
+                               this many (1 = every batch; <= 0 means 1)   */
+    int32_t pad_;
 } qed_surrogate_cfg;
 
 /* Train on the device (table must be on the device).  Synchronous at the
@@ -353,6 +358,33 @@ int32_t qed_schwinger_rate(qed_context* ctx, const qed_cells* cells, void* rate_
 int32_t qed_schwinger_pairs(qed_context* ctx, const qed_cells* cells, double cell_volume, double dt,
                             double weight, uint64_t seed, uint64_t step, qed_append* electrons,
                             qed_append* positrons, void* stream);
+
+/* ------------------------------------------------------------------- push
+ * A particle push in prescribed analytic fields, to close the loop of the
+ * QED sub-step without a field solver: the benchmark geometries of Sec. 5.1
+ * (electrons in a static magnetic field perpendicular to their motion, and
+ * electrons counter-propagating with a circularly polarised plane wave). */
+typedef enum { QED_FIELD_UNIFORM = 0, QED_FIELD_CP_WAVE = 1 } qed_field_kind;
+typedef struct {
+    int32_t kind;         /* qed_field_kind                                  */
+    int32_t direction;    /* CP wave: +1 propagates along +x, -1 along -x    */
+    double e0[3];         /* UNIFORM: E (V/m)                                */
+    double b0[3];         /* UNIFORM: B (T)                                  */
+    double amplitude;     /* CP wave: |E| (V/m); E = A (0, cos ph, sin ph),
+                             B = (direction x_hat) x E / c,
+                             ph = 2 pi (direction x - c t)/wavelength + phase */
+    double wavelength;    /* CP wave: m                                      */
+    double phase;         /* CP wave: rad                                    */
+} qed_field;
+
+/* Advance one species by dt from time t: leptons by the relativistic Boris
+ * scheme (u at half steps, charge -e for electrons and +e for positrons,
+ * fields at the old position and time t), photons on straight lines at c;
+ * positions x, y, z (device, m, same dtype as the particles) are updated,
+ * and the fields at the new position and time t + dt are written into the
+ * particles' E/B arrays (what qed_step reads next).  Ions are refused. */
+int32_t qed_push(qed_context* ctx, const qed_particles* p, void* x, void* y, void* z, const qed_field* field,
+                 double t, double dt, void* stream);
 
 /* ------------------------------------------------------------------- misc */
 const char* qed_last_error(void);

@@ -34,7 +34,7 @@ EXPORTS = (
     "qed_table_rate", "qed_table_sample",
     "qed_surrogate_train", "qed_surrogate_from_host", "qed_surrogate_get_params",
     "qed_surrogate_forward", "qed_surrogate_grad", "qed_surrogate_sample", "qed_surrogate_destroy",
-    "qed_schwinger_rate", "qed_schwinger_pairs",
+    "qed_schwinger_rate", "qed_schwinger_pairs", "qed_push",
     "qed_last_error", "qed_version",
 )
 
@@ -77,10 +77,16 @@ class CellsC(C.Structure):
                [("n", C.c_int64), ("cell_id_base", C.c_int64), ("dtype", C.c_int32), ("pad_", C.c_int32)]
 
 
+class FieldC(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("direction", C.c_int32), ("e0", C.c_double * 3), ("b0", C.c_double * 3),
+                ("amplitude", C.c_double), ("wavelength", C.c_double), ("phase", C.c_double)]
+
+
 class SurrogateCfg(C.Structure):
     _fields_ = [("process", C.c_int32), ("n_samples", C.c_int32), ("batch", C.c_int32),
                 ("steps", C.c_int32), ("lr", C.c_float), ("probe_tol", C.c_float),
-                ("chi_lo", C.c_double), ("chi_hi", C.c_double), ("seed", C.c_uint64)]
+                ("chi_lo", C.c_double), ("chi_hi", C.c_double), ("seed", C.c_uint64),
+                ("probe_every", C.c_int32), ("pad_", C.c_int32)]
 
 
 _lib = None
@@ -123,6 +129,7 @@ def lib():
             "qed_surrogate_sample": [vp, vp, vp, vp, i64, vp],
             "qed_schwinger_rate": [vp, P(CellsC), vp, vp],
             "qed_schwinger_pairs": [vp, P(CellsC), d, d, d, u64, u64, P(AppendC), P(AppendC), vp],
+            "qed_push": [vp, P(ParticlesC), vp, vp, vp, P(FieldC), d, d, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -370,8 +377,8 @@ class Surrogate:
 
     @staticmethod
     def cfg(process, chi_lo, chi_hi, n_samples=1 << 22, batch=16384, steps=20000, lr=3e-3, probe_tol=0.5,
-            seed=7):
-        return SurrogateCfg(process, n_samples, batch, steps, lr, probe_tol, chi_lo, chi_hi, seed)
+            seed=7, probe_every=16):
+        return SurrogateCfg(process, n_samples, batch, steps, lr, probe_tol, chi_lo, chi_hi, seed, probe_every, 0)
 
     @classmethod
     def train(cls, ctx, table, cfg, stream=None):
@@ -427,3 +434,20 @@ def schwinger_pairs(ctx, c: CellsC, cell_volume, dt, weight, seed, step, electro
                     positrons: AppendBuffer, stream=None):
     check(lib().qed_schwinger_pairs(ctx.h, C.byref(c), float(cell_volume), float(dt), float(weight), seed, step,
                                     C.byref(electrons.c), C.byref(positrons.c), _stream(stream)))
+
+
+# -------------------------------------------------------------------- push
+FIELD_UNIFORM, FIELD_CP_WAVE = 0, 1
+
+
+def uniform_field(e0=(0.0, 0.0, 0.0), b0=(0.0, 0.0, 0.0)) -> FieldC:
+    return FieldC(FIELD_UNIFORM, 1, (C.c_double * 3)(*e0), (C.c_double * 3)(*b0), 0.0, 0.0, 0.0)
+
+
+def cp_wave(amplitude, wavelength, direction=1, phase=0.0) -> FieldC:
+    return FieldC(FIELD_CP_WAVE, direction, (C.c_double * 3)(), (C.c_double * 3)(), amplitude, wavelength, phase)
+
+
+def push(ctx, p: ParticlesC, x, y, z, field: FieldC, t, dt, stream=None):
+    check(lib().qed_push(ctx.h, C.byref(p), _ptr(x), _ptr(y), _ptr(z), C.byref(field), float(t), float(dt),
+                         _stream(stream)))
