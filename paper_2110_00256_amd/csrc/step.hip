@@ -125,17 +125,22 @@ __device__ __forceinline__ void write_product(const AppendDev& o, int64_t slot, 
 
 // Surrogate sampling for the events of one wave (all 64 lanes call it
 // together; `valid` marks lanes holding an event).  Lanes outside the
-// trained domain use the table; one probe lane per wave also evaluates the
-// table and, if the network is off by more than probe_tol in its output
-// space, the whole wave falls back to the table.  Returns the network-side
-// sample (QS: ln xi; BW: xi), or NAN where the caller must use the table.
-__device__ __forceinline__ float surr_wave_sample(const StepArgs& a, const SurrogateDev& sv, const TableDev& tab,
-                                                  bool valid, float chi, float u, float* lds_y, int64_t* stats) {
+// trained domain use the table.  When `probe` is set (wave-uniform) one
+// lane also evaluates the table and, if the network is off by more than
+// probe_tol in its output space, the whole wave falls back to the table and
+// `failed` is set.  Returns the network-side sample (QS: ln xi; BW: xi), or
+// NAN where the caller must use the table; `batch` tells whether the
+// network ran for this wave.
+__device__ __forceinline__ float surr_wave_sample(const SurrogateDev& sv, const TableDev& tab, bool valid, float chi,
+                                                  float u, float* lds_y, bool probe, bool& batch, bool& failed) {
     float x0 = 0.f, x1 = 0.f;
     const bool inside = valid && surr_inputs(sv, chi, u, x0, x1);
     const unsigned long long in_mask = __ballot(inside);
-    if (in_mask == 0ULL) return __builtin_nanf("");
+    batch = in_mask != 0ULL;
+    failed = false;
+    if (!batch) return __builtin_nanf("");
     const float y = surr_forward_wave(sv, x0, x1, lds_y);
+    if (!probe) return inside ? surr_output(sv, chi, u, y) : __builtin_nanf("");
     // probe: the first lane with an in-domain event
     const unsigned probe_lane = static_cast<unsigned>(__builtin_ctzll(in_mask));
     float err = 0.f;
@@ -150,12 +155,8 @@ __device__ __forceinline__ float surr_wave_sample(const StepArgs& a, const Surro
         err = fabsf(y - surr_target_of(sv.process, chi, u, ref));
     }
     err = __shfl(err, static_cast<int>(probe_lane));
-    const bool fallback = !(err <= sv.probe_tol);
-    if (stats && __lane_id() == probe_lane) {
-        atomicAdd(reinterpret_cast<unsigned long long*>(stats + QED_STAT_SURR_BATCHES), 1ULL);
-        if (fallback) atomicAdd(reinterpret_cast<unsigned long long*>(stats + QED_STAT_SURR_FALLBACK), 1ULL);
-    }
-    if (fallback || !inside) return __builtin_nanf("");
+    failed = !(err <= sv.probe_tol);
+    if (failed || !inside) return __builtin_nanf("");
     return surr_output(sv, chi, u, y);
 }
 
@@ -177,7 +178,7 @@ __device__ __forceinline__ T bw_xi(const StepArgs& a, bool valid, bool have, T c
 }
 
 template <typename T, int kChiMode, bool kSurr>
-__global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
+__device__ __forceinline__ void step_body(const StepArgs& a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int nbw = a.bw.n_chi > 0 ? a.bw.n_chi : 0;
     const int nqs = a.qs.n_chi > 0 ? a.qs.n_chi : 0;
@@ -204,6 +205,11 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
         for (int i = tid; i < nbw; i += kBlock) t_bw[i] = ln_rate_ptr<T>(a.bw)[i];
     if (a.qs.ln_rate64 || a.qs.ln_rate32)
         for (int i = tid; i < nqs; i += kBlock) t_qs[i] = ln_rate_ptr<T>(a.qs)[i];
+
+    // launch statistics, accumulated per block and added once at the end
+    // (one atomic per counter and block instead of one per chunk or batch)
+    unsigned long long n_updates = 0, n_qs_events = 0, n_bw_events = 0, n_kept = 0;
+    unsigned long long n_surr_batches = 0, n_surr_fallbacks = 0;   // lane 0 of each wave
 
     for (;;) {
         __syncthreads();
@@ -323,8 +329,11 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
             surr_on = photon ? a.use_bw_surr : a.use_qs_surr;
             if (surr_on) {
                 const SurrogateDev& sv = photon ? a.bw_surr : a.qs_surr;
-        #pragma unroll 1
-        for (int e0 = 0; e0 + wave * 64 < total; e0 += kBlock) {
+                // one wave batch in probe_every is probed (rounds staggered
+                // by chunk); after a failed probe the wave keeps the table for
+                // the rest of the chunk
+                bool failed_before = false;
+                for (int e0 = 0; e0 + wave * 64 < total; e0 += kBlock) {
                     const int e = e0 + tid;
                     const bool valid = e < total;
                     const int le = valid ? evlist[e] : 0;
@@ -333,7 +342,16 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
                     if (valid)
                         r = static_cast<float>(dev::draws(a.seed, static_cast<unsigned long long>(S.id_base + c.begin + le),
                                                           a.step, static_cast<unsigned long long>(S.species), 0ULL).u[0]);
-                    const float v = surr_wave_sample(a, sv, photon ? a.bw : a.qs, valid, chi, r, s_surr_y[wave], a.stats);
+                    const bool probe = ((k + (e0 >> 8)) % sv.probe_every) == 0;
+                    bool batch, failed;
+                    float v = surr_wave_sample(sv, photon ? a.bw : a.qs, valid, chi, r, s_surr_y[wave], probe, batch,
+                                               failed);
+                    failed_before = failed_before || failed;
+                    if (failed_before) v = __builtin_nanf("");
+                    if (lane == 0 && batch) {
+                        ++n_surr_batches;
+                        if (failed_before) ++n_surr_fallbacks;
+                    }
                     const bool have = valid && !__builtin_isnan(v);
                     if (have) s_chi[le] = v;
                     const unsigned long long m = __ballot(have);
@@ -422,15 +440,12 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
                     *a.ph.count = s_base0 + incl;
                 }
             }
-            if (a.stats) {
-                atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + QED_STAT_UPDATES),
-                          static_cast<unsigned long long>(c.len));
-                atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + (photon ? QED_STAT_BW_EVENTS
-                                                                                 : QED_STAT_QS_EVENTS)),
-                          static_cast<unsigned long long>(total));
-                if (!photon)
-                    atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + QED_STAT_PHOTONS_KEPT),
-                              static_cast<unsigned long long>(prods));
+            n_updates += c.len;
+            if (photon) {
+                n_bw_events += total;
+            } else {
+                n_qs_events += total;
+                n_kept += prods;
             }
         }
         __syncthreads();
@@ -506,7 +521,47 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
             }
         }
     }
+    if (a.stats) {
+        auto add = [&](int slot, unsigned long long v) {
+            if (v) atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + slot), v);
+        };
+        if (tid == 0) {
+            add(QED_STAT_UPDATES, n_updates);
+            add(QED_STAT_QS_EVENTS, n_qs_events);
+            add(QED_STAT_BW_EVENTS, n_bw_events);
+            add(QED_STAT_PHOTONS_KEPT, n_kept);
+        }
+        if (lane == 0) {
+            add(QED_STAT_SURR_BATCHES, n_surr_batches);
+            add(QED_STAT_SURR_FALLBACK, n_surr_fallbacks);
+        }
+    }
 }
+
+// The table-path kernel, and the surrogate-path kernel with a register
+// budget that keeps two waves per SIMD (the network's MFMA fragments would
+// otherwise take the whole register file and leave one).
+constexpr int kSurrWavesPerEu = 2;
+
+template <typename T, int kChiMode>
+__global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
+    step_body<T, kChiMode, false>(a);
+}
+
+template <typename T, int kChiMode>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kSurrWavesPerEu)))
+step_kernel_surr(StepArgs a) {
+    step_body<T, kChiMode, true>(a);
+}
+
+template <typename T, int kChiMode, bool kSurr>
+struct StepKernel {
+    static constexpr auto fn = step_kernel<T, kChiMode>;
+};
+template <typename T, int kChiMode>
+struct StepKernel<T, kChiMode, true> {
+    static constexpr auto fn = step_kernel_surr<T, kChiMode>;
+};
 
 // Elementwise kernels (grid-stride) -----------------------------------------
 template <typename T, bool kPhoton>
@@ -593,11 +648,11 @@ template <typename T, bool kSurr>
 hipError_t launch_step_t(const StepArgs& a, int grid, hipStream_t s) {
     const size_t lds = step_lds_bytes(a, sizeof(T));
     if (a.chi_mode == QED_CHI_COMP32)
-        hipLaunchKernelGGL((step_kernel<T, QED_CHI_COMP32, kSurr>), dim3(grid), dim3(kBlock), lds, s, a);
+        hipLaunchKernelGGL((StepKernel<T, QED_CHI_COMP32, kSurr>::fn), dim3(grid), dim3(kBlock), lds, s, a);
     else if (a.chi_mode == QED_CHI_FP32)
-        hipLaunchKernelGGL((step_kernel<T, QED_CHI_FP32, kSurr>), dim3(grid), dim3(kBlock), lds, s, a);
+        hipLaunchKernelGGL((StepKernel<T, QED_CHI_FP32, kSurr>::fn), dim3(grid), dim3(kBlock), lds, s, a);
     else
-        hipLaunchKernelGGL((step_kernel<T, QED_CHI_FP64, kSurr>), dim3(grid), dim3(kBlock), lds, s, a);
+        hipLaunchKernelGGL((StepKernel<T, QED_CHI_FP64, kSurr>::fn), dim3(grid), dim3(kBlock), lds, s, a);
     return hipGetLastError();
 }
 
@@ -620,11 +675,11 @@ int occupancy(const StepArgs& a, size_t lds) {
     int per_cu = 0;
     hipError_t e;
     if (a.chi_mode == QED_CHI_COMP32)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_kernel<T, QED_CHI_COMP32, kSurr>, kBlock, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, StepKernel<T, QED_CHI_COMP32, kSurr>::fn, kBlock, lds);
     else if (a.chi_mode == QED_CHI_FP32)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_kernel<T, QED_CHI_FP32, kSurr>, kBlock, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, StepKernel<T, QED_CHI_FP32, kSurr>::fn, kBlock, lds);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_kernel<T, QED_CHI_FP64, kSurr>, kBlock, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, StepKernel<T, QED_CHI_FP64, kSurr>::fn, kBlock, lds);
     return (e == hipSuccess && per_cu > 0) ? per_cu : 1;
 }
 }  // namespace

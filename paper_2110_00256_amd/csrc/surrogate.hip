@@ -35,6 +35,7 @@ struct qed_surrogate {
         s.chi_lo = static_cast<float>(cfg.chi_lo);
         s.chi_hi = static_cast<float>(cfg.chi_hi);
         s.probe_tol = cfg.probe_tol;
+        s.probe_every = cfg.probe_every > 0 ? cfg.probe_every : 1;
         return s;
     }
 };

@@ -38,6 +38,7 @@ struct SurrogateDev {
     float mid, inv_half;     // x0 = (ln chi - mid) * inv_half
     float chi_lo, chi_hi;
     float probe_tol;
+    int32_t probe_every;     // probe one wave batch in this many (>= 1)
 };
 
 typedef short surr_v4s __attribute__((ext_vector_type(4)));

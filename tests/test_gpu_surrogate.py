@@ -158,8 +158,8 @@ def test_step_with_surrogate_probe_and_counts(ctx, tables):
     cfg_b = Q.Surrogate.cfg(Q.BW, 1e-3, 1e3, n_samples=1 << 21, steps=3000, probe_tol=1.0)
     sq, _ = Q.Surrogate.train(ctx, qs, cfg_q)
     sb, _ = Q.Surrogate.train(ctx, bw, cfg_b)
-    cfg_q0 = Q.Surrogate.cfg(Q.QS, 1e-3, 1e3, probe_tol=0.0)
-    cfg_b0 = Q.Surrogate.cfg(Q.BW, 1e-3, 1e3, probe_tol=0.0)
+    cfg_q0 = Q.Surrogate.cfg(Q.QS, 1e-3, 1e3, probe_tol=0.0, probe_every=1)
+    cfg_b0 = Q.Surrogate.cfg(Q.BW, 1e-3, 1e3, probe_tol=0.0, probe_every=1)
     sq0 = Q.Surrogate.from_host(qs, cfg_q0, sq.params())
     sb0 = Q.Surrogate.from_host(bw, cfg_b0, sb.params())
     el, ph = QI.c2_population(seed=8, n=1 << 18)
