@@ -128,6 +128,35 @@ typedef struct qed_context qed_context;
 int32_t qed_context_create(int32_t device, qed_context** out);
 void qed_context_destroy(qed_context* ctx);
 
+/* ------------------------------------------------------------------ units
+ * The unit system of the caller's arrays and scalars for every call made
+ * through a context (Sec. 4: the interface accepts SI units and normalised
+ * units with a reference frequency or length; internally the paper works in
+ * Heaviside-Lorentz units with 1 MeV as reference energy).  Default SI:
+ * E in V/m, B in T, momenta as u = p/(m_e c), time in s, energies in
+ * m_e c^2.  Normalised (c = e = m_e = 1): E in m_e c w/e, B in m_e w/e, time
+ * in 1/w, u as in SI, energies in m_e c^2, with w the reference angular
+ * frequency given directly or as w = 2 pi c / lambda from a reference
+ * wavelength (this library's reading of "reference length").
+ * Heaviside-Lorentz (hbar = c = eps0 = 1, unit 1 MeV): E and B in MeV^2
+ * (charge sqrt(4 pi alpha)), momenta in MeV/c, time in 1/MeV, energies in
+ * MeV.  Tables are dimensionless and shared by all systems.  Applies to
+ * qed_chi_*, qed_evolve_optical_depth, qed_step and the generate calls
+ * (fields, momenta, dt, photon_min_energy; products are written in the
+ * same units); qed_push and the Schwinger calls take SI. */
+typedef enum {
+    QED_UNITS_SI = 0,
+    QED_UNITS_NORM_OMEGA = 1,    /* ref = reference angular frequency (1/s) */
+    QED_UNITS_NORM_LAMBDA = 2,   /* ref = reference wavelength (m)          */
+    QED_UNITS_HL_MEV = 3         /* ref unused                              */
+} qed_unit_system;
+typedef struct {
+    int32_t system;
+    int32_t pad_;
+    double ref;
+} qed_units;
+int32_t qed_context_set_units(qed_context* ctx, const qed_units* units);
+
 /* -------------------------------------------------------------- particles
  * One species' SoA arrays in device memory, n elements of `dtype` each.
  * tau is read and written; u is written by photon emission; w (weight,
@@ -250,6 +279,12 @@ typedef struct {
     double photon_min_energy;
     int32_t chi_mode;
     int32_t pad_;
+    double chi_qed_min;            /* > 0: below this chi a particle keeps its
+                                      optical depth; photons do nothing and
+                                      leptons lose the classically radiated
+                                      energy (2/3)(alpha m c^2/hbar) chi^2 dt
+                                      m c^2 along u (Sec. 6, WarpX's minimum
+                                      quantum parameter).  0: off */
 } qed_step_desc;
 
 /* stats layout (accumulated, device int64): */

@@ -92,7 +92,7 @@ def lib():
         L.orc_sample_qs_lnxi.argtypes = [C.POINTER(_Table), d, d]; L.orc_sample_qs_lnxi.restype = d
         L.orc_init_optical_depth.argtypes = [C.POINTER(_Particles), u64]
         L.orc_step.argtypes = [C.POINTER(_Table), C.POINTER(_Table), C.POINTER(_Particles), d, u64, u64,
-                               d, _u8p, C.POINTER(_Append), C.POINTER(_Append)]
+                               d, d, _u8p, C.POINTER(_Append), C.POINTER(_Append)]
         L.orc_step.restype = C.c_int64
         L.orc_generate.argtypes = [C.POINTER(_Table), C.POINTER(_Table), C.POINTER(_Particles), _u8p,
                                    u64, u64, d, C.POINTER(_Append), C.POINTER(_Append)]
@@ -338,12 +338,13 @@ def init_optical_depth(p: Particles, seed: int):
 
 
 def step(bw: Table, qs: Table, p: Particles, dt: float, seed: int, step_idx: int,
-         a1: Append, a2: Append | None = None, photon_min_energy: float = 0.0, flags=None):
+         a1: Append, a2: Append | None = None, photon_min_energy: float = 0.0, flags=None,
+         chi_qed_min: float = 0.0):
     if a2 is None:
         a2 = Append(0)
     fl = None if flags is None else _ptr(flags, _u8p)
     return lib().orc_step(bw.cstruct, qs.cstruct, p.cstruct, dt, seed, step_idx,
-                          photon_min_energy, fl, a1.cstruct, a2.cstruct)
+                          photon_min_energy, chi_qed_min, fl, a1.cstruct, a2.cstruct)
 
 
 def generate(bw: Table, qs: Table, p: Particles, flags: np.ndarray, seed: int, step_idx: int,

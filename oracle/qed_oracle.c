@@ -623,10 +623,29 @@ typedef struct {
     double pa[5], pb[5];  /* product records: ux uy uz w tau */
 } orc_event_out;
 
-/* Evolve one particle; returns 1 on an event.  Products go to *ev. */
+/* Classical radiation below the QED threshold (Sec. 6: below a minimum
+ * quantum parameter pair production is ignored and photon emission is
+ * treated classically).  The classical model taken here is the radiation
+ * drag of the ultra-relativistic Landau-Lifshitz force: the particle loses
+ * the energy radiated classically, P = (2/3) (alpha m c^2/hbar) chi^2 m c^2,
+ * along its direction of motion over dt; gamma' = max(1, gamma - dgamma),
+ * u' = u sqrt(gamma'^2 - 1)/|u|. */
+static void classical_drag(double u[3], double chi, double dt) {
+    double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    if (!(u2 > 0.0)) return;
+    double gamma = sqrt(1.0 + u2);
+    double dg = (2.0 / 3.0) * orc_rate_prefactor() * chi * chi * dt;
+    double gp = gamma - dg;
+    double sc = gp > 1.0 ? sqrt((gp - 1.0) * (gp + 1.0)) / sqrt(u2) : 0.0;
+    u[0] *= sc; u[1] *= sc; u[2] *= sc;
+}
+
+/* Evolve one particle; returns 1 on an event.  Products go to *ev.  With
+ * chi_qed_min > 0, a particle whose chi is below it keeps its optical depth:
+ * photons do nothing, leptons take the classical drag instead. */
 static int step_one(const orc_table* bw, const orc_table* qs, orc_particles* p, int64_t i,
                     double dt, uint64_t seed, uint64_t step, double photon_min_energy,
-                    orc_event_out* ev) {
+                    double chi_qed_min, orc_event_out* ev) {
     int photon = (p->species == ORC_PHOTON);
     double u[3] = {p->ux[i], p->uy[i], p->uz[i]};
     double e[3] = {p->ex[i], p->ey[i], p->ez[i]};
@@ -635,9 +654,16 @@ static int step_one(const orc_table* bw, const orc_table* qs, orc_particles* p, 
     double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     double um = sqrt(u2);
     double gamma = photon ? um : sqrt(1.0 + u2);
+    ev->nprod = 0;
+    if (chi_qed_min > 0.0 && chi < chi_qed_min) {
+        if (!photon) {
+            classical_drag(u, chi, dt);
+            p->ux[i] = u[0]; p->uy[i] = u[1]; p->uz[i] = u[2];
+        }
+        return 0;
+    }
     double rate = photon ? orc_rate_bw(bw, chi, gamma) : orc_rate_qs(qs, chi, gamma);
     double tau = p->tau[i] - rate * dt;
-    ev->nprod = 0;
     if (!(tau < 0.0)) {
         p->tau[i] = tau;
         return 0;
@@ -684,13 +710,13 @@ static int step_one(const orc_table* bw, const orc_table* qs, orc_particles* p, 
  * same slot.  Products beyond capacity are dropped; count always holds the
  * total required.  flags (nullable) receives 1 for an event, else 0. */
 int64_t orc_step(const orc_table* bw, const orc_table* qs, orc_particles* p, double dt,
-                 uint64_t seed, uint64_t step, double photon_min_energy, uint8_t* flags,
+                 uint64_t seed, uint64_t step, double photon_min_energy, double chi_qed_min, uint8_t* flags,
                  orc_append* a1, orc_append* a2) {
     orc_event_out* ev = (orc_event_out*)malloc(sizeof(orc_event_out) * (size_t)(p->n > 0 ? p->n : 1));
     int64_t events = 0;
 #pragma omp parallel for reduction(+ : events) schedule(static)
     for (int64_t i = 0; i < p->n; ++i) {
-        int e = step_one(bw, qs, p, i, dt, seed, step, photon_min_energy, &ev[i]);
+        int e = step_one(bw, qs, p, i, dt, seed, step, photon_min_energy, chi_qed_min, &ev[i]);
         if (flags) flags[i] = (uint8_t)e;
         events += e;
     }
@@ -723,7 +749,7 @@ int64_t orc_generate(const orc_table* bw, const orc_table* qs, orc_particles* p,
         if (!flags[i]) continue;
         p->tau[i] = -1.0;   /* forces the event branch with rate*dt = 0 */
         orc_event_out ev;
-        step_one(bw, qs, p, i, 0.0, seed, step, photon_min_energy, &ev);
+        step_one(bw, qs, p, i, 0.0, seed, step, photon_min_energy, 0.0, &ev);
         int64_t parent = p->id_base + i;
         if (ev.nprod == 1) {
             put(a1, a1->count, ev.pa[0], ev.pa[1], ev.pa[2], ev.pa[3], ev.pa[4], parent);

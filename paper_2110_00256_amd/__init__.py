@@ -28,7 +28,7 @@ SURR_NPARAM = 64 * 2 + 64 + 64 * 64 + 64 + 64 + 1
 EXPORTS = (
     "qed_table_generate", "qed_table_from_host", "qed_table_save", "qed_table_load",
     "qed_table_host_data", "qed_table_to_device", "qed_table_destroy", "qed_table_generate_device",
-    "qed_context_create", "qed_context_destroy",
+    "qed_context_create", "qed_context_destroy", "qed_context_set_units",
     "qed_chi_lepton", "qed_chi_photon", "qed_init_optical_depth", "qed_evolve_optical_depth",
     "qed_generate_pairs", "qed_generate_photon_and_update_momentum", "qed_step", "qed_read_count",
     "qed_table_rate", "qed_table_sample",
@@ -69,12 +69,19 @@ class StepDescC(C.Structure):
                 ("electrons", C.POINTER(AppendC)), ("positrons", C.POINTER(AppendC)),
                 ("flags", C.POINTER(C.c_void_p)), ("stats", C.c_void_p), ("dt", C.c_double),
                 ("seed", C.c_uint64), ("step", C.c_uint64), ("photon_min_energy", C.c_double),
-                ("chi_mode", C.c_int32), ("pad_", C.c_int32)]
+                ("chi_mode", C.c_int32), ("pad_", C.c_int32), ("chi_qed_min", C.c_double)]
 
 
 class CellsC(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("ex", "ey", "ez", "bx", "by", "bz")] + \
                [("n", C.c_int64), ("cell_id_base", C.c_int64), ("dtype", C.c_int32), ("pad_", C.c_int32)]
+
+
+class UnitsC(C.Structure):
+    _fields_ = [("system", C.c_int32), ("pad_", C.c_int32), ("ref", C.c_double)]
+
+
+UNITS_SI, UNITS_NORM_OMEGA, UNITS_NORM_LAMBDA, UNITS_HL_MEV = 0, 1, 2, 3
 
 
 class FieldC(C.Structure):
@@ -110,6 +117,7 @@ def lib():
             "qed_table_host_data": [vp, P(vp), P(vp), P(TableParams)],
             "qed_table_to_device": [vp, vp],
             "qed_context_create": [i32, P(vp)],
+            "qed_context_set_units": [vp, P(UnitsC)],
             "qed_chi_lepton": [vp, P(ParticlesC), i32, vp, vp],
             "qed_chi_photon": [vp, P(ParticlesC), i32, vp, vp],
             "qed_init_optical_depth": [vp, P(ParticlesC), u64, vp],
@@ -229,6 +237,10 @@ class Context:
         check(lib().qed_context_create(device, C.byref(h)))
         self.h = h
 
+    def set_units(self, system, ref=0.0):
+        """Unit system of the arrays and scalars of every call through this context."""
+        check(lib().qed_context_set_units(self.h, C.byref(UnitsC(system, 0, float(ref)))))
+
     def __del__(self):
         if getattr(self, "h", None) is not None and self.h.value and _lib is not None:
             _lib.qed_context_destroy(self.h)
@@ -335,7 +347,7 @@ class StepDesc:
 
     def __init__(self, sets, bw=None, qs=None, photons=None, electrons=None, positrons=None, tiles=None,
                  flags=None, stats=None, dt=0.0, seed=1, step=0, photon_min_energy=0.0, chi_mode=CHI_FP64,
-                 bw_surrogate=None, qs_surrogate=None):
+                 bw_surrogate=None, qs_surrogate=None, chi_qed_min=0.0):
         self._sets = (ParticlesC * len(sets))(*sets)
         self._keep = [bw, qs, photons, electrons, positrons, tiles, flags, stats, bw_surrogate, qs_surrogate]
         fl = None
@@ -353,7 +365,8 @@ class StepDesc:
             self._sets, len(sets), 0 if tiles is None else len(self._tiles) // 3, tl,
             C.pointer(photons.c) if photons else None, C.pointer(electrons.c) if electrons else None,
             C.pointer(positrons.c) if positrons else None, fl,
-            stats.data_ptr() if stats is not None else None, dt, seed, step, photon_min_energy, chi_mode, 0)
+            stats.data_ptr() if stats is not None else None, dt, seed, step, photon_min_energy, chi_mode, 0,
+            chi_qed_min)
 
     def set_step(self, step):
         self.c.step = step

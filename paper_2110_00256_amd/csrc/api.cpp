@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "constants.hpp"
 #include "internal.hpp"
 #include "surrogate_api.hpp"
 
@@ -255,6 +256,46 @@ extern "C" int32_t qed_context_create(int32_t device, qed_context** out) {
     return QED_OK;
 }
 
+extern "C" int32_t qed_context_set_units(qed_context* ctx, const qed_units* units) {
+    if (!ctx || !units) { set_error("context/units is null"); return QED_ERR_INVALID; }
+    Units u;
+    constexpr double kPi = 3.141592653589793;
+    switch (units->system) {
+        case QED_UNITS_SI:
+            break;
+        case QED_UNITS_NORM_OMEGA:
+        case QED_UNITS_NORM_LAMBDA: {
+            if (!(units->ref > 0.0) || !std::isfinite(units->ref)) { set_error("reference must be > 0"); return QED_ERR_INVALID; }
+            // c = e = m_e = 1 with reference angular frequency w (or w = 2 pi c / lambda)
+            const double w = units->system == QED_UNITS_NORM_OMEGA ? units->ref : 2.0 * kPi * kC / units->ref;
+            u.e = kMe * kC * w / kQe;
+            u.b = kMe * w / kQe;
+            u.t = 1.0 / w;
+            u.length = kC / w;
+            break;
+        }
+        case QED_UNITS_HL_MEV: {
+            // hbar = c = eps0 = 1, energy unit 1 MeV; the HL charge is sqrt(4 pi alpha)
+            const double mev = 1e6 * kQe;                          // J
+            const double me_mev = kMe * kC * kC / mev;
+            const double e_hl = std::sqrt(4.0 * kPi * kAlpha);
+            u.e = e_hl * mev * mev / (kHbar * kC * kQe);           // V/m per MeV^2
+            u.b = u.e / kC;                                         // T per MeV^2
+            u.u = 1.0 / me_mev;                                     // p in MeV/c -> p/(m_e c)
+            u.inv_u = me_mev;
+            u.t = kHbar / mev;                                      // s per MeV^-1
+            u.length = kHbar * kC / mev;                            // m per MeV^-1
+            u.energy = 1.0 / me_mev;
+            break;
+        }
+        default:
+            set_error("unknown unit system");
+            return QED_ERR_INVALID;
+    }
+    ctx->units = u;
+    return QED_OK;
+}
+
 extern "C" void qed_context_destroy(qed_context* c) {
     if (!c) return;
     int cur = 0;
@@ -283,6 +324,7 @@ static int32_t chi_common(qed_context* ctx, const qed_particles* p, int32_t chi_
     if (!chi_out) { set_error("chi_out is null"); return QED_ERR_INVALID; }
     ElemArgs a{};
     a.set = to_set(*p, nullptr);
+    a.units = ctx->units;
     a.chi_out = chi_out;
     a.chi_mode = chi_mode;
     a.is_photon = photon;
@@ -328,7 +370,8 @@ extern "C" int32_t qed_evolve_optical_depth(qed_context* ctx, const qed_table* r
     ElemArgs a{};
     a.set = to_set(*p, flags);
     a.table = rate->view();
-    a.dt = dt;
+    a.dt = dt * ctx->units.t;
+    a.units = ctx->units;
     a.chi_mode = chi_mode;
     a.is_photon = photon;
     const hipError_t e = launch_evolve(a, p->dtype, static_cast<hipStream_t>(stream));
@@ -342,6 +385,7 @@ static int32_t run_chunks(qed_context* ctx, const qed_step_desc* d, bool generat
     if (d->n_tiles < 0 || (d->n_tiles > 0 && !d->tiles)) { set_error("bad tiles"); return QED_ERR_INVALID; }
     if (!generate_only && (!std::isfinite(d->dt) || d->dt < 0.0)) { set_error("dt must be finite and >= 0"); return QED_ERR_INVALID; }
     if (!(d->photon_min_energy >= 0.0)) { set_error("photon_min_energy must be >= 0"); return QED_ERR_INVALID; }
+    if (!(d->chi_qed_min >= 0.0)) { set_error("chi_qed_min must be >= 0"); return QED_ERR_INVALID; }
     if (d->chi_mode < QED_CHI_FP64 || d->chi_mode > QED_CHI_FP32) { set_error("bad chi_mode"); return QED_ERR_INVALID; }
     const int dtype = d->sets[0].dtype;
     bool any_lepton = false, any_photon = false;
@@ -382,10 +426,13 @@ static int32_t run_chunks(qed_context* ctx, const qed_step_desc* d, bool generat
     a.el = to_append(any_photon ? d->electrons : nullptr);
     a.po = to_append(any_photon ? d->positrons : nullptr);
     a.stats = d->stats;
-    a.dt = d->dt;
+    a.dt = d->dt * ctx->units.t;
+    a.units = ctx->units;
     a.seed = d->seed;
     a.step = d->step;
-    a.photon_min_energy = d->photon_min_energy;
+    a.photon_min_energy = d->photon_min_energy * ctx->units.energy;
+    a.chi_qed_min = d->chi_qed_min;
+    a.drag = (2.0 / 3.0) * kRateR0 * a.dt;
     a.chi_mode = dtype == QED_FP64 ? QED_CHI_FP64 : d->chi_mode;
     if ((d->bw_surrogate || d->qs_surrogate) && dtype != QED_FP32) {
         set_error("surrogate sampling runs on the FP32 path only");

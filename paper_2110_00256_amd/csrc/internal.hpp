@@ -64,6 +64,15 @@ struct ChunkDesc {
     int32_t pad_;
 };
 
+// Caller units -> the library's (E in V/m, B in T, u = p/(m_e c), t in s,
+// energies in m_e c^2).  All 1 for SI.
+struct Units {
+    double e = 1.0, b = 1.0, u = 1.0, inv_u = 1.0;   // multiply a caller value by these
+    double t = 1.0;        // seconds per caller time unit
+    double energy = 1.0;   // m_e c^2 per caller energy unit
+    double length = 1.0;   // metres per caller length unit
+};
+
 struct StepArgs {
     SetDev sets[kMaxSets];
     int32_t n_sets;
@@ -83,6 +92,9 @@ struct StepArgs {
     unsigned long long seed, step;
     double photon_min_energy;
     int32_t chi_mode;
+    double chi_qed_min;             // 0: no classical regime
+    double drag;                    // (2/3) (alpha m c^2 / hbar) dt
+    Units units;
 };
 
 struct ElemArgs {
@@ -93,6 +105,7 @@ struct ElemArgs {
     unsigned long long seed;
     int32_t chi_mode;
     int32_t is_photon;
+    Units units;
 };
 
 // Kernel launchers (step.hip).  Return hipError_t of the launch.
@@ -142,6 +155,7 @@ struct qed_context {
     std::vector<qedmi::ChunkDesc> h_chunks_cached;
     void* d_scratch = nullptr;              // general device scratch (Schwinger scan offsets)
     int64_t scratch_cap = 0;                // bytes
+    qedmi::Units units;                     // caller unit system (qed_context_set_units)
 };
 
 namespace qedmi {

@@ -160,6 +160,25 @@ __device__ __forceinline__ float surr_wave_sample(const SurrogateDev& sv, const 
     return surr_output(sv, chi, u, y);
 }
 
+// Classical radiation below the QED threshold (Sec. 6): the energy
+// radiated classically, (2/3)(alpha m c^2/hbar) chi^2 dt in m c^2 (`drag`
+// holds the factor in front of chi^2), is taken from the particle along its
+// direction of motion: gamma' = max(1, gamma - dgamma), u' = u
+// sqrt(gamma'^2 - 1)/|u|.
+template <typename T>
+__device__ __forceinline__ void classical_drag(const SetDev& S, int64_t j, T ux, T uy, T uz, T chi, double drag,
+                                               double inv_u) {
+    const double x = ux, y = uy, z = uz;
+    const double u2 = x * x + y * y + z * z;
+    if (!(u2 > 0.0)) return;
+    const double c = chi;
+    const double gp = sqrt(1.0 + u2) - drag * c * c;
+    const double sc = gp > 1.0 ? sqrt((gp - 1.0) * (gp + 1.0)) / sqrt(u2) : 0.0;
+    st<T>(S.p[0], j, static_cast<T>(x * sc * inv_u));
+    st<T>(S.p[1], j, static_cast<T>(y * sc * inv_u));
+    st<T>(S.p[2], j, static_cast<T>(z * sc * inv_u));
+}
+
 // Sampled photon fraction ln xi for a lepton event.  `cs` is the event's
 // LDS word: the surrogate's sample when `have`, else chi for the table.
 template <typename T>
@@ -240,9 +259,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                     const int64_t j = c.begin + loc;
                     ev = S.flags[j] != 0;
                     if (ev) {
-                        const T ux = ld<T>(S.p[0], j), uy = ld<T>(S.p[1], j), uz = ld<T>(S.p[2], j);
-                        const T ex = ld<T>(S.p[3], j), ey = ld<T>(S.p[4], j), ez = ld<T>(S.p[5], j);
-                        const T bx = ld<T>(S.p[6], j), by = ld<T>(S.p[7], j), bz = ld<T>(S.p[8], j);
+                        const T su = static_cast<T>(a.units.u), se = static_cast<T>(a.units.e),
+                                sb = static_cast<T>(a.units.b);
+                        const T ux = su * ld<T>(S.p[0], j), uy = su * ld<T>(S.p[1], j), uz = su * ld<T>(S.p[2], j);
+                        const T ex = se * ld<T>(S.p[3], j), ey = se * ld<T>(S.p[4], j), ez = se * ld<T>(S.p[5], j);
+                        const T bx = sb * ld<T>(S.p[6], j), by = sb * ld<T>(S.p[7], j), bz = sb * ld<T>(S.p[8], j);
                         s_chi[loc] = photon
                             ? static_cast<T>(dev::chi_of<T, true>(kChiMode, ux, uy, uz, ex, ey, ez, bx, by, bz).chi)
                             : static_cast<T>(dev::chi_of<T, false>(kChiMode, ux, uy, uz, ex, ey, ez, bx, by, bz).chi);
@@ -266,6 +287,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                     const int64_t j = c.begin + (loc < c.len ? loc : 0);
 #pragma unroll
                     for (int q = 0; q < 10; ++q) v[b][q] = ldnt<T>(S.p[q], j);
+                    // caller units -> u = p/(m_e c), V/m, T (factors 1 for SI)
+#pragma unroll
+                    for (int q = 0; q < 9; ++q)
+                        v[b][q] *= static_cast<T>(q < 3 ? a.units.u : q < 6 ? a.units.e : a.units.b);
                 }
 #pragma unroll
                 for (int b = 0; b < kBatch; ++b) {
@@ -285,8 +310,15 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                             chi = static_cast<T>(cg.chi);
                             rate = dev::rate_qs<T>(t_qs, a.qs, chi, static_cast<T>(cg.gamma));
                         }
-                        const T tn = v[b][9] - rate * dt;
+                        T tn = v[b][9] - rate * dt;
                         ev = tn < T(0);
+                        if (a.chi_qed_min > 0.0 && static_cast<double>(chi) < a.chi_qed_min) {
+                            // classical regime: tau is kept, leptons radiate classically
+                            ev = false;
+                            tn = v[b][9];
+                            if (!photon)
+                                classical_drag<T>(S, j, v[b][0], v[b][1], v[b][2], chi, a.drag, a.units.inv_u);
+                        }
                         if (ev) s_chi[loc] = chi;
                         else stnt<T>(S.p[9], j, tn);
                         if (S.flags) S.flags[j] = static_cast<uint8_t>(ev);
@@ -399,7 +431,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 if (e < total) {
                     const int le = evlist[e];
                     const int64_t j = c.begin + le;
-                    const double ux = ld<T>(S.p[0], j), uy = ld<T>(S.p[1], j), uz = ld<T>(S.p[2], j);
+                    const T su = static_cast<T>(a.units.u);
+                    const double ux = su * ld<T>(S.p[0], j), uy = su * ld<T>(S.p[1], j), uz = su * ld<T>(S.p[2], j);
                     const double u2 = ux * ux + uy * uy + uz * uz;
                     const T gg = static_cast<T>(u2 / (sqrt(1.0 + u2) + 1.0)) * s_chi[le];
                     keep = gg >= static_cast<T>(a.photon_min_energy);
@@ -456,13 +489,14 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
         // ...) with the next event's u and w loads in flight while the
         // current one is computed.
         {
+            const T su = static_cast<T>(a.units.u), iu = static_cast<T>(a.units.inv_u);
             int e = tid;
             T nux = T(0), nuy = T(0), nuz = T(0), nw = T(1);
             if (e < total) {
                 const int64_t jn = c.begin + evlist[e];
-                nux = ld<T>(S.p[0], jn);
-                nuy = ld<T>(S.p[1], jn);
-                nuz = ld<T>(S.p[2], jn);
+                nux = su * ld<T>(S.p[0], jn);
+                nuy = su * ld<T>(S.p[1], jn);
+                nuz = su * ld<T>(S.p[2], jn);
                 if (S.p[10]) nw = ld<T>(S.p[10], jn);
             }
 #pragma unroll 1
@@ -472,9 +506,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 const T ux = nux, uy = nuy, uz = nuz, w = nw;
                 if (e + kBlock < total) {
                     const int64_t jn = c.begin + evlist[e + kBlock];
-                    nux = ld<T>(S.p[0], jn);
-                    nuy = ld<T>(S.p[1], jn);
-                    nuz = ld<T>(S.p[2], jn);
+                    nux = su * ld<T>(S.p[0], jn);
+                    nuy = su * ld<T>(S.p[1], jn);
+                    nuz = su * ld<T>(S.p[2], jn);
                     if (S.p[10]) nw = ld<T>(S.p[10], jn);
                 }
                 const int64_t parent = S.id_base + j;
@@ -487,8 +521,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 const T t2 = static_cast<T>(-log(d.u[2]));
                 if (photon) {
                     const bool esel = static_cast<T>(d.u[0]) <= T(0.5);
-                    const T sx = xi * ux, sy = xi * uy, sz = xi * uz;
-                    const T ox = ux - sx, oy = uy - sy, oz = uz - sz;
+                    const T sx = xi * ux * iu, sy = xi * uy * iu, sz = xi * uz * iu;
+                    const T ox = ux * iu - sx, oy = uy * iu - sy, oz = uz * iu - sz;
                     const T te = t1, tp = t2;
                     const long long slot = slot0 + e;
                     write_product<T>(a.el, s_base0 + slot, esel ? sx : ox, esel ? sy : oy, esel ? sz : oz, w, te,
@@ -504,9 +538,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                     const T um = static_cast<T>(sqrt(u2));
                     const T sc = um > T(0) ? gg / um : T(0);
                     const T px = sc * ux, py = sc * uy, pz = sc * uz;
-                    st<T>(S.p[0], j, ux - px);
-                    st<T>(S.p[1], j, uy - py);
-                    st<T>(S.p[2], j, uz - pz);
+                    st<T>(S.p[0], j, (ux - px) * iu);
+                    st<T>(S.p[1], j, (uy - py) * iu);
+                    st<T>(S.p[2], j, (uz - pz) * iu);
                     st<T>(S.p[9], j, t1);
                     bool keep = true;
                     long long rank = e;
@@ -516,7 +550,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                         rank = kpref[e >> 6] + __popcll(m & ((1ULL << (e & 63)) - 1ULL));
                     }
                     if (keep)
-                        write_product<T>(a.ph, s_base0 + slot0 + rank, px, py, pz, w, t2, parent);
+                        write_product<T>(a.ph, s_base0 + slot0 + rank, px * iu, py * iu, pz * iu, w, t2, parent);
                 }
             }
         }
@@ -567,12 +601,14 @@ struct StepKernel<T, kChiMode, true> {
 template <typename T, bool kPhoton>
 __global__ void __launch_bounds__(256) chi_kernel(ElemArgs a) {
     const SetDev& S = a.set;
+    const T su = static_cast<T>(a.units.u), se = static_cast<T>(a.units.e), sb = static_cast<T>(a.units.b);
     for (int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; j < S.n;
          j += int64_t(gridDim.x) * blockDim.x) {
-        const dev::ChiGamma cg = dev::chi_of<T, kPhoton>(a.chi_mode, ld<T>(S.p[0], j), ld<T>(S.p[1], j),
-                                                         ld<T>(S.p[2], j), ld<T>(S.p[3], j), ld<T>(S.p[4], j),
-                                                         ld<T>(S.p[5], j), ld<T>(S.p[6], j), ld<T>(S.p[7], j),
-                                                         ld<T>(S.p[8], j));
+        const dev::ChiGamma cg = dev::chi_of<T, kPhoton>(a.chi_mode, su * ld<T>(S.p[0], j), su * ld<T>(S.p[1], j),
+                                                         su * ld<T>(S.p[2], j), se * ld<T>(S.p[3], j),
+                                                         se * ld<T>(S.p[4], j), se * ld<T>(S.p[5], j),
+                                                         sb * ld<T>(S.p[6], j), sb * ld<T>(S.p[7], j),
+                                                         sb * ld<T>(S.p[8], j));
         st<T>(a.chi_out, j, static_cast<T>(cg.chi));
     }
 }
@@ -596,12 +632,14 @@ __global__ void __launch_bounds__(256) evolve_kernel(ElemArgs a) {
     __syncthreads();
     const SetDev& S = a.set;
     const T dt = static_cast<T>(a.dt);
+    const T su = static_cast<T>(a.units.u), se = static_cast<T>(a.units.e), sb = static_cast<T>(a.units.b);
     for (int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; j < S.n;
          j += int64_t(gridDim.x) * blockDim.x) {
-        const dev::ChiGamma cg = dev::chi_of<T, kPhoton>(a.chi_mode, ld<T>(S.p[0], j), ld<T>(S.p[1], j),
-                                                         ld<T>(S.p[2], j), ld<T>(S.p[3], j), ld<T>(S.p[4], j),
-                                                         ld<T>(S.p[5], j), ld<T>(S.p[6], j), ld<T>(S.p[7], j),
-                                                         ld<T>(S.p[8], j));
+        const dev::ChiGamma cg = dev::chi_of<T, kPhoton>(a.chi_mode, su * ld<T>(S.p[0], j), su * ld<T>(S.p[1], j),
+                                                         su * ld<T>(S.p[2], j), se * ld<T>(S.p[3], j),
+                                                         se * ld<T>(S.p[4], j), se * ld<T>(S.p[5], j),
+                                                         sb * ld<T>(S.p[6], j), sb * ld<T>(S.p[7], j),
+                                                         sb * ld<T>(S.p[8], j));
         const T rate = kPhoton ? dev::rate_bw<T>(tab, a.table, static_cast<T>(cg.chi), static_cast<T>(cg.gamma))
                                : dev::rate_qs<T>(tab, a.table, static_cast<T>(cg.chi), static_cast<T>(cg.gamma));
         const T tn = ld<T>(S.p[9], j) - rate * dt;

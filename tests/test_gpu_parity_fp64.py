@@ -84,7 +84,7 @@ def test_evolve_matches_oracle(ctx, tabs):
 
 
 def _run_steps(ctx, tabs, n_e, n_g, steps, seed=1, dt=1e-16, threshold=0.0, cap=None, tiles=None,
-               check_each_step=True):
+               check_each_step=True, chi_qed_min=0.0):
     """Run the fused step on GPU and the oracle side by side; compare."""
     (bw, qs), (obw, oqs) = tabs
     el, ph = QI.c1_population(seed=seed, n=max(n_e, n_g))
@@ -111,7 +111,8 @@ def _run_steps(ctx, tabs, n_e, n_g, steps, seed=1, dt=1e-16, threshold=0.0, cap=
     fg = torch.zeros(max(n_g, 1), dtype=torch.uint8, device="cuda")
     stats = torch.zeros(Q.STATS_LEN, dtype=torch.int64, device="cuda")
     desc = Q.StepDesc([pe, pg], bw=bw, qs=qs, photons=ph_b, electrons=el_b, positrons=po_b,
-                      flags=[fe, fg], stats=stats, dt=dt, seed=seed, photon_min_energy=threshold, tiles=tiles)
+                      flags=[fe, fg], stats=stats, dt=dt, seed=seed, photon_min_energy=threshold, tiles=tiles,
+                      chi_qed_min=chi_qed_min)
     total_events = 0
     pu = {"ph": [], "el": [], "po": []}   # parent |u| of every product, in slot order
     # A particle's momentum is compared on the scale of the largest |u| it has
@@ -126,8 +127,9 @@ def _run_steps(ctx, tabs, n_e, n_g, steps, seed=1, dt=1e-16, threshold=0.0, cap=
         ofe = np.zeros(max(n_e, 1), dtype=np.uint8)
         ofg = np.zeros(max(n_g, 1), dtype=np.uint8)
         if tiles is None:
-            total_events += O.step(obw, oqs, oe, dt, seed, s, o_ph, photon_min_energy=threshold, flags=ofe[:n_e])
-            total_events += O.step(obw, oqs, og, dt, seed, s, o_el, o_po, flags=ofg[:n_g])
+            total_events += O.step(obw, oqs, oe, dt, seed, s, o_ph, photon_min_energy=threshold, flags=ofe[:n_e],
+                                   chi_qed_min=chi_qed_min)
+            total_events += O.step(obw, oqs, og, dt, seed, s, o_el, o_po, flags=ofg[:n_g], chi_qed_min=chi_qed_min)
         else:
             total_events += _oracle_tiles(obw, oqs, [oe, og], tiles, dt, seed, s, o_ph, o_el, o_po, threshold,
                                           [ofe, ofg])
@@ -201,6 +203,15 @@ def test_tiles_follow_tile_order(ctx, tabs):
 def test_photon_threshold(ctx, tabs):
     ev, (ph_b, _, _), (o_ph, _, _) = _run_steps(ctx, tabs, 30000, 10, 3, seed=5, threshold=2.0)
     assert 0 < o_ph.count < ev
+
+
+def test_qed_threshold_classical_regime(ctx, tabs):
+    """WarpX's minimum quantum parameter (Sec. 6): below chi_qed_min photons
+    keep their optical depth and leptons radiate classically; about half of
+    the parity workload's particles are below 0.5."""
+    ev_on, _, _ = _run_steps(ctx, tabs, 20000, 20000, 4, seed=12, chi_qed_min=0.5)
+    ev_off, _, _ = _run_steps(ctx, tabs, 20000, 20000, 4, seed=12)
+    assert 0 < ev_on < ev_off
 
 
 def test_capacity_overflow_counts_and_prefix(ctx, tabs):

@@ -232,3 +232,41 @@ def test_capacity_and_threshold(tables64):
     assert a_t.count == int(keep.sum()) < a_b.count
     np.testing.assert_array_equal(a_t["parent"], a_b["parent"][keep])
     np.testing.assert_array_equal(thr["ux"], base["ux"])
+
+
+def test_qed_threshold_classical_drag():
+    """Below chi_qed_min (Sec. 6, WarpX's minimum quantum parameter): no
+    optical-depth evolution; photons untouched; leptons lose the classically
+    radiated energy (2/3) (alpha m c^2/hbar) chi^2 dt (in m c^2) along u."""
+    import math
+    import qed_inputs as QI
+    qs = O.Table(O.QS, 1e-3, 1e2, 16, 16)
+    bw = O.Table(O.BW, 1e-3, 1e2, 16, 16)
+    n = 4
+    d = {k: np.zeros(n) for k in QI.FIELDS}
+    d["ux"][:] = [-100.0, -2000.0, -5000.0, -0.5]
+    d["uy"][:] = [3.0, 0.0, 10.0, 0.1]
+    d["ey"][:] = 1e13
+    d["bz"][:] = 1e13 / QI.C_LIGHT
+    d["w"][:] = 1.0
+    chi = O.chi_array(d, False)
+    thr = float(np.sort(chi)[2] * 1.0001)          # three below, one above
+    p = O.Particles(d, O.ELECTRON, tau=np.full(n, 0.5))
+    flags = np.zeros(n, dtype=np.uint8)
+    dt = 1e-16
+    O.step(bw, qs, p, dt, 1, 0, O.Append(n), flags=flags, chi_qed_min=thr)
+    r0 = 7.2973525693e-3 * QI.M_E * QI.C_LIGHT ** 2 / QI.HBAR
+    for i in range(n):
+        u0 = np.array([d["ux"][i], d["uy"][i], 0.0])
+        u1 = np.array([p["ux"][i], p["uy"][i], p["uz"][i]])
+        if chi[i] < thr:
+            assert p["tau"][i] == 0.5 and flags[i] == 0
+            g0, g1 = math.sqrt(1 + u0 @ u0), math.sqrt(1 + u1 @ u1)
+            assert g0 - g1 == pytest.approx((2 / 3) * r0 * chi[i] ** 2 * dt, rel=1e-9)
+            assert np.allclose(np.cross(u0, u1), 0.0, atol=1e-12 * (u0 @ u0))   # along u
+        else:
+            assert p["tau"][i] != 0.5                                    # evolved as usual
+    # photons below the threshold are left alone
+    ph = O.Particles(d, O.PHOTON, tau=np.full(n, 0.5))
+    O.step(bw, qs, ph, dt, 1, 0, O.Append(n), O.Append(n), chi_qed_min=1e9)
+    assert np.all(ph["tau"] == 0.5) and np.all(ph["ux"] == d["ux"])
