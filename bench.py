@@ -150,7 +150,7 @@ def run_path(Q, torch, ctx, tables, pops, dtype, steps, warmup, dt, chi_mode, se
     return res
 
 
-def cpu_baseline(pops_small, tables_params, dt, seed=1):
+def cpu_baseline(pops_small, tables_params, dt, seed=1, min_seconds=10.0, max_steps=400):
     """The oracle, as it stands, on a bounded sample of the same workload."""
     from oracle import oracle as O
     n_chi, n_frac, rng = tables_params
@@ -162,14 +162,15 @@ def cpu_baseline(pops_small, tables_params, dt, seed=1):
     O.init_optical_depth(oe, seed)
     O.init_optical_depth(og, seed)
     n = oe.n + og.n
-    a1, a2, a3 = O.Append(n), O.Append(n), O.Append(n)
-    steps = 2
-    log(f"cpu_baseline: timing {steps} oracle steps over {n} particles")
+    a1, a2, a3 = O.Append(oe.n), O.Append(og.n), O.Append(og.n)
+    log(f"cpu_baseline: timing oracle steps over {n} particles for at least {min_seconds} s")
+    steps = 0
     t0 = time.perf_counter()
-    for s in range(steps):
+    while steps < max_steps and (steps == 0 or time.perf_counter() - t0 < min_seconds):
         a1.count = a2.count = a3.count = 0
-        O.step(obw, oqs, oe, dt, seed, s, a1)
-        O.step(obw, oqs, og, dt, seed, s, a2, a3)
+        O.step(obw, oqs, oe, dt, seed, steps, a1)
+        O.step(obw, oqs, og, dt, seed, steps, a2, a3)
+        steps += 1
     wall = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return dict(value=steps * n / wall, unit="particle updates/s", cores=cores, kind="oracle",
@@ -251,6 +252,88 @@ def fullstep(Q, torch, QI, args):
     print(json.dumps(out), flush=True)
 
 
+# The paper's own kernel timings (Sec. 4, Table comp, NVIDIA Quadro GV100,
+# CUDA), ms for 1e8 particles, FP64 / FP32: context for the paper workload.
+PAPER_GV100_MS = {
+    "bw_evol": (14.52, 7.43), "bw_prod": (29.94, 15.70),
+    "qs_evol": (14.62, 7.39), "qs_em": (26.88, 14.15),
+}
+
+
+def paper(Q, torch, QI, args):
+    """The paper's benchmark (Sec. 4): 1e8 particles with E, B and p
+    components uniform in +-E_s/100, +-E_s/(100c), +-1 GeV/c, optical depth
+    Exp(1); 256-point rate tables and 256x256 CDF tables, chi_min 1e-3 (QS)
+    and 0.02 (BW), chi_max 1e3; each of the four standalone calls applied to
+    every particle (for pair production and photon emission: every particle
+    is flagged and produces), timed on the device, FP64 and FP32."""
+    n = args.paper_n
+    log(f"paper: generating 2 x {n} particles")
+    pops = (QI.paper_uniform(n, seed=1, stream=0), QI.paper_uniform(n, seed=1, stream=1))
+    ctx = Q.Context(0)
+    log("paper: tables")
+    bw = Q.Table.generate(Q.BW, 0.02, 1e3, 256, 256).to_device()
+    qs = Q.Table.generate(Q.QS, 1e-3, 1e3, 256, 256, 1e-12).to_device()
+    out = {"workload": f"paper Sec. 4 benchmark: {n} particles per call, uniform E, B, p; 256 / 256x256 tables; "
+                       "every particle produces in bw_prod and qs_em",
+           "particles": n, "runs": args.steps}
+    for dt_name, tdt, idx in (("f64", torch.float64, 0), ("f32", torch.float32, 1)):
+        dev = []
+        for pop in pops:
+            d = {k: torch.as_tensor(v).to("cuda", dtype=tdt) for k, v in pop.items()}
+            d["tau"] = torch.empty_like(d["ux"])
+            dev.append(d)
+        pl = Q.particles(dev[0], Q.ELECTRON, 0)
+        pg = Q.particles(dev[1], Q.PHOTON, n)
+        Q.init_optical_depth(ctx, pl, 1)
+        Q.init_optical_depth(ctx, pg, 1)
+        saved = [{k: d[k].clone() for k in ("ux", "uy", "uz", "tau")} for d in dev]
+        flags = torch.ones(n, dtype=torch.uint8, device="cuda")
+        ph = Q.AppendBuffer(n, tdt)
+        el, po = Q.AppendBuffer(n, tdt), Q.AppendBuffer(n, tdt)
+        dt = 1e-16
+
+        def restore():
+            for d, s0 in zip(dev, saved):
+                for k, v in s0.items():
+                    d[k].copy_(v)
+            for b in (ph, el, po):
+                b.reset()
+
+        calls = {
+            "bw_evol": lambda: Q.evolve_optical_depth(ctx, bw, pg, dt),
+            "bw_prod": lambda: Q.generate_pairs(ctx, bw, pg, flags, 1, 0, el, po),
+            "qs_evol": lambda: Q.evolve_optical_depth(ctx, qs, pl, dt),
+            "qs_em": lambda: Q.generate_photon_and_update_momentum(ctx, qs, pl, flags, 1, 0, ph),
+        }
+        res = {}
+        for name, fn in calls.items():
+            restore()
+            fn()
+            ms = []
+            for _ in range(args.steps):
+                restore()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn()
+                e1.record()
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            if name == "bw_prod":
+                assert int(el.count.item()) == n and int(po.count.item()) == n
+            if name == "qs_em":
+                assert int(ph.count.item()) == n
+            m = float(np.mean(ms))
+            gv = PAPER_GV100_MS[name][idx]
+            res[name] = {"ms_mean": m, "updates_per_s": n / (m * 1e-3), "gv100_cuda_ms_for_1e8": gv,
+                         "speedup_vs_gv100": gv * (n / 1e8) / m}
+            log(f"paper {dt_name} {name}: {m:.3f} ms ({res[name]['speedup_vs_gv100']:.1f}x the GV100 time)")
+        out[dt_name] = res
+        del dev, saved, ph, el, po, flags
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,12 +344,15 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-steps", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-log2n", type=int, default=17)
+    ap.add_argument("--cpu-sample-log2n", type=int, default=22,
+                    help="the oracle is timed on the first 2^k particles of each species, whole steps, >= 10 s")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
-    ap.add_argument("--workload", choices=("cone", "fullstep"), default="cone",
+    ap.add_argument("--workload", choices=("cone", "fullstep", "paper"), default="cone",
                     help="cone: the default roofline workload; fullstep: 4 species in lognormal tiles, "
-                         "Gaussian pulse, FP32 table and FP32+surrogate paths")
+                         "Gaussian pulse, FP32 table and FP32+surrogate paths; paper: the paper's own "
+                         "benchmark of the four standalone calls")
+    ap.add_argument("--paper-n", type=int, default=100_000_000, help="particles of the paper workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -288,6 +374,9 @@ def main():
 
     if args.workload == "fullstep":
         fullstep(Q, torch, QI, args)
+        return
+    if args.workload == "paper":
+        paper(Q, torch, QI, args)
         return
 
     n = 1 << args.log2n

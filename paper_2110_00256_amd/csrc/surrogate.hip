@@ -312,14 +312,13 @@ __global__ void __launch_bounds__(256) surr_refresh_w2(const float* params, uint
 
 // Forward on raw network inputs x[n][2] (FP32) -> y[n].
 __global__ void __launch_bounds__(256) surr_forward_kernel(SurrogateDev s, const float* x, float* y, long long n) {
-    __shared__ float lds_y[4][64];
     const int wave = threadIdx.x >> 6, lane = static_cast<int>(__lane_id());
     for (long long b = (static_cast<long long>(blockIdx.x) * 4 + wave) * 64; b < n;
          b += static_cast<long long>(gridDim.x) * 256) {
         const long long i = b + lane;
         const bool ok = i < n;
         const float x0 = ok ? x[2 * i] : 0.f, x1 = ok ? x[2 * i + 1] : 0.f;
-        const float out = surr_forward_wave(s, x0, x1, lds_y[wave]);
+        const float out = surr_forward_wave(s, x0, x1);
         if (ok) y[i] = out;
     }
 }
@@ -327,7 +326,6 @@ __global__ void __launch_bounds__(256) surr_forward_kernel(SurrogateDev s, const
 // Sampling for (chi, u) arrays: surrogate inside its domain, table outside.
 __global__ void __launch_bounds__(256) surr_sample_kernel(SurrogateDev s, TableDev t, const float* chi, const float* u,
                                                           float* out, long long n) {
-    __shared__ float lds_y[4][64];
     const int wave = threadIdx.x >> 6, lane = static_cast<int>(__lane_id());
     for (long long b = (static_cast<long long>(blockIdx.x) * 4 + wave) * 64; b < n;
          b += static_cast<long long>(gridDim.x) * 256) {
@@ -336,7 +334,7 @@ __global__ void __launch_bounds__(256) surr_sample_kernel(SurrogateDev s, TableD
         const float c = valid ? chi[i] : 1.f, r = valid ? u[i] : 0.5f;
         float x0 = 0.f, x1 = 0.f;
         const bool inside = valid && surr_inputs(s, c, r, x0, x1);
-        const float yv = surr_forward_wave(s, x0, x1, lds_y[wave]);
+        const float yv = surr_forward_wave(s, x0, x1);
         if (!valid) continue;
         float res;
         if (inside) {

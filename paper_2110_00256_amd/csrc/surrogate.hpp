@@ -44,9 +44,12 @@ struct SurrogateDev {
 typedef short surr_v4s __attribute__((ext_vector_type(4)));
 typedef float surr_v4f __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ float surr_silu(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU and its derivative with the hardware reciprocal (1 ulp) in place of
+// an IEEE division: the activation is two transcendental instructions.
+__device__ __forceinline__ float surr_sigmoid(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ __forceinline__ float surr_silu(float z) { return z * surr_sigmoid(z); }
 __device__ __forceinline__ float surr_dsilu(float z) {
-    const float s = 1.0f / (1.0f + __expf(-z));
+    const float s = surr_sigmoid(z);
     return s * (1.0f + z * (1.0f - s));
 }
 
@@ -120,65 +123,72 @@ __device__ __forceinline__ float surr_output(const SurrogateDev& s, float chi, f
 }
 
 // Forward pass for the 64 samples of one wave: lane l owns sample l
-// (inputs x0, x1); returns that sample's output.  lds_y: 64 floats private
-// to the calling wave.  W2 fragments are read from global (L2-resident).
-__device__ __forceinline__ float surr_forward_wave(const SurrogateDev& s, float x0, float x1, float* lds_y) {
+// (inputs x0, x1) and gets that sample's output.  The layers run in the
+// transposed orientation (hidden units along the MFMA rows, samples along
+// its columns), so that each layer's output fragment is the next layer's
+// operand fragment in the same lane and nothing is exchanged between layers:
+//   layer 1  Z^T  = [W1 | b1 | 0] [x0 x1 1 0]^T: FP32 MFMA 16x16x4, one per
+//            16 hidden units (K = 4 holds the two inputs and the bias);
+//   layer 2  H^T  = W2 silu(Z)^T: BF16 MFMA 16x16x16, FP32 accumulation;
+//   layer 3  y    = b3 + w3 . silu(H + b2): each lane sums its 16 hidden
+//            units, two cross-lane adds sum the four lane groups of a column.
+// Samples are taken 16 at a time (one MFMA column block).
+__device__ __forceinline__ float surr_forward_wave(const SurrogateDev& s, float x0, float x1) {
     const int lane = static_cast<int>(__lane_id());
     const int col = lane & 15, grp = lane >> 4;
     const float* p = s.p;
-    surr_v4s bw2[4][4];   // B[k][n] = W2[n][k], k = ks*16 + 4 grp + e, n = nt*16 + col
+    // layer-1 A operand: row = hidden unit ks*16 + col, k = grp
+    float a1[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        const int h = ks * 16 + col;
+        a1[ks] = grp == 0 ? p[kOffW1 + 2 * h] : grp == 1 ? p[kOffW1 + 2 * h + 1] : grp == 2 ? p[kOffB1 + h] : 0.0f;
+    }
+    // layer-2 A operand: A[i][k] = W2[nt*16 + i][ks*16 + k], i = col, k = 4 grp + e
+    surr_v4s aw2[4][4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks)
-            bw2[nt][ks] = *reinterpret_cast<const surr_v4s*>(s.w2 + (nt * 16 + col) * 64 + ks * 16 + 4 * grp);
-    float b2[4], w3[4];
+            aw2[nt][ks] = *reinterpret_cast<const surr_v4s*>(s.w2 + (nt * 16 + col) * 64 + ks * 16 + 4 * grp);
+    // layer-2 output rows held by this lane: hidden unit nt*16 + 4 grp + e
+    float b2[4][4], w3[4][4];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        b2[nt] = p[kOffB2 + nt * 16 + col];
-        w3[nt] = p[kOffW3 + nt * 16 + col];
-    }
-    const float b3 = p[kOffB3];
-    // one 16-sample group at a time keeps the live registers of the fused
-    // step kernel low (its streaming phase needs the occupancy)
-#pragma unroll 1
-    for (int q = 0; q < 4; ++q) {
-        const float sx0 = __shfl(x0, q * 16 + col);
-        const float sx1 = __shfl(x1, q * 16 + col);
-        surr_v4s a[4];
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int k = ks * 16 + 4 * grp + e;
-                const float z = p[kOffW1 + 2 * k] * sx0 + p[kOffW1 + 2 * k + 1] * sx1 + p[kOffB1 + k];
-                a[ks][e] = surr_bf16(surr_silu(z));
-            }
-        }
-        float part[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            surr_v4f acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[ks], bw2[nt][ks], acc, 0, 0, 0);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) part[e] += w3[nt] * surr_silu(acc[e] + b2[nt]);
-        }
+    for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-#pragma unroll
-            for (int o = 1; o < 16; o <<= 1) part[e] += __shfl_xor(part[e], o);
+            b2[nt][e] = p[kOffB2 + nt * 16 + 4 * grp + e];
+            w3[nt][e] = p[kOffW3 + nt * 16 + 4 * grp + e];
         }
-        if (col == 0) {
+    const float b3 = p[kOffB3];
+    float y = 0.0f;
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) {
+        // layer-1 B operand: k = grp, column = sample q*16 + col
+        const float sx0 = __shfl(x0, q * 16 + col);
+        const float sx1 = __shfl(x1, q * 16 + col);
+        const float bx = grp == 0 ? sx0 : grp == 1 ? sx1 : grp == 2 ? 1.0f : 0.0f;
+        surr_v4s h1[4];   // layer-2 B operand: k = hidden ks*16 + 4 grp + e, column = sample
 #pragma unroll
-            for (int e = 0; e < 4; ++e) lds_y[q * 16 + 4 * grp + e] = part[e] + b3;
+        for (int ks = 0; ks < 4; ++ks) {
+            const surr_v4f zero = {0.0f, 0.0f, 0.0f, 0.0f};
+            const surr_v4f z = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], bx, zero, 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) h1[ks][e] = surr_bf16(surr_silu(z[e]));
         }
+        float part = 0.0f;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            surr_v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aw2[nt][ks], h1[ks], acc, 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) part += w3[nt][e] * surr_silu(acc[e] + b2[nt][e]);
+        }
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (grp == q) y = part + b3;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const float y = lds_y[lane];
-    __builtin_amdgcn_wave_barrier();
     return y;
 }
 
