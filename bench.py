@@ -342,7 +342,7 @@ def main():
     ap.add_argument("--log2n", type=int, default=24, help="particles per species = 2^log2n")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--surrogate-steps", type=int, default=40000)
+    ap.add_argument("--surrogate-steps", type=int, default=320000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2n", type=int, default=22,
                     help="the oracle is timed on the first 2^k particles of each species, whole steps, >= 10 s")

@@ -261,6 +261,26 @@ __device__ __forceinline__ T tload(const float* p, int i) { return static_cast<T
 template <typename T>
 __device__ __forceinline__ T tload(const Bf16* p, int i) { return static_cast<T>(bf16_to_f32(p[i].bits)); }
 
+// Entry k of a row pair (both rows' values with one load).
+template <typename T>
+__device__ __forceinline__ void tload2(const double* pp, int k, T& a0, T& a1) {
+    const double2 v = *reinterpret_cast<const double2*>(pp + 2 * k);
+    a0 = static_cast<T>(v.x);
+    a1 = static_cast<T>(v.y);
+}
+template <typename T>
+__device__ __forceinline__ void tload2(const float* pp, int k, T& a0, T& a1) {
+    const float2 v = *reinterpret_cast<const float2*>(pp + 2 * k);
+    a0 = static_cast<T>(v.x);
+    a1 = static_cast<T>(v.y);
+}
+template <typename T>
+__device__ __forceinline__ void tload2(const Bf16* pp, int k, T& a0, T& a1) {
+    const unsigned v = *reinterpret_cast<const unsigned*>(pp + 2 * k);
+    a0 = static_cast<T>(bf16_to_f32(static_cast<uint16_t>(v & 0xffffu)));
+    a1 = static_cast<T>(bf16_to_f32(static_cast<uint16_t>(v >> 16)));
+}
+
 // BW: dN/dt = (alpha m c^2/hbar) (chi_gamma/gamma_gamma) T(chi_gamma)
 // (Sec. 2.1); ln T interpolated linearly in ln chi (Sec. 3.1); outside the
 // table, the asymptotes of the integral definition matched at the edges:
@@ -323,33 +343,40 @@ __device__ __forceinline__ const Bf16* cdf_ptr<Bf16>(const TableDev& t) {
 }
 
 
-// Upper-bound binary search over the row interpolated between p0 and p1 with
-// weight f: starting from [0, nf - 1], halve while hi - lo > 1, keeping lo
-// when the interpolated value at mid is <= r; returns lo.  Two levels per
-// round: the probe at mid and both possible next probes are loaded
-// together, so the chain of dependent table reads is half as long, and the
-// decisions (hence the result) are those of the plain one-level search.
+// Row interpolated between the two rows of a pair with weight f, at k.
 template <typename T, typename S>
-__device__ __forceinline__ int upper_bound_row(const S* p0, const S* p1, T f, T r, int nf) {
+__device__ __forceinline__ T pair_value(const S* pp, T f, int k) {
+    T a0, a1;
+    tload2<T>(pp, k, a0, a1);
+    return a0 + f * (a1 - a0);
+}
+
+// Upper-bound binary search over the row pair pp interpolated with weight f:
+// starting from [0, nf - 1], halve while hi - lo > 1, keeping lo when the
+// interpolated value at mid is <= r; returns lo.  Two levels per round: the
+// probe at mid and both possible next probes are loaded together, so the
+// chain of dependent table reads is half as long, and the decisions (hence
+// the result) are those of the plain one-level search.
+template <typename T, typename S>
+__device__ __forceinline__ int upper_bound_row(const S* pp, T f, T r, int nf) {
     int lo = 0, hi = nf - 1;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         const int ml = (lo + mid) >> 1;   // next probe if the search goes left
         const int mr = (mid + hi) >> 1;   // next probe if it goes right
-        const T a0 = tload<T>(p0, mid), a1 = tload<T>(p1, mid);
-        const T l0 = tload<T>(p0, ml), l1 = tload<T>(p1, ml);
-        const T r0 = tload<T>(p0, mr), r1 = tload<T>(p1, mr);
-        const T vm = a0 + f * (a1 - a0);
+        const T vm = pair_value<T, S>(pp, f, mid);
+        const T vl = pair_value<T, S>(pp, f, ml);
+        const T vr = pair_value<T, S>(pp, f, mr);
         if (vm <= r) {
             lo = mid;
             if (hi - lo > 1) {
-                if (r0 + f * (r1 - r0) <= r) lo = mr;
+                if (vr <= r) lo = mr;
                 else hi = mr;
             }
         } else {
             hi = mid;
             if (hi - lo > 1) {
-                if (l0 + f * (l1 - l0) <= r) lo = ml;
+                if (vl <= r) lo = ml;
                 else hi = ml;
             }
         }
@@ -368,11 +395,10 @@ __device__ __forceinline__ T sample_bw(const TableDev& t, T chi, T r, bool& elec
     electron = (r <= T(0.5));
     if (!electron) r = T(1) - r;
     const int nf = t.n_frac;
-    const S* p0 = cdf_ptr<S>(t) + static_cast<size_t>(n) * nf;
-    const S* p1 = p0 + nf;
-    const int lo = upper_bound_row<T, S>(p0, p1, f, r, nf);
-    const T pa = tload<T>(p0, lo) + f * (tload<T>(p1, lo) - tload<T>(p0, lo));
-    const T pb = tload<T>(p0, lo + 1) + f * (tload<T>(p1, lo + 1) - tload<T>(p0, lo + 1));
+    const S* pp = cdf_ptr<S>(t) + 2 * static_cast<size_t>(n) * nf;
+    const int lo = upper_bound_row<T, S>(pp, f, r, nf);
+    const T pa = pair_value<T, S>(pp, f, lo);
+    const T pb = pair_value<T, S>(pp, f, lo + 1);
     const T scale = T(0.5) / static_cast<T>(nf - 1);
     const T xa = scale * static_cast<T>(lo), xb = scale * static_cast<T>(lo + 1);
     return xa + (r - pa) * (xb - xa) / (pb - pa);
@@ -388,15 +414,14 @@ __device__ __forceinline__ T sample_qs_lnxi(const TableDev& t, T chi, T r) {
     T f;
     row_pos<T>(t, chi, n, f);
     const int nf = t.n_frac;
-    const S* p0 = cdf_ptr<S>(t) + static_cast<size_t>(n) * nf;
-    const S* p1 = p0 + nf;
+    const S* pp = cdf_ptr<S>(t) + 2 * static_cast<size_t>(n) * nf;
     const T lr = dlog(r);
     const T lmin = static_cast<T>(t.ln_frac_min);
-    const T l0 = tload<T>(p0, 0) + f * (tload<T>(p1, 0) - tload<T>(p0, 0));
+    const T l0 = pair_value<T, S>(pp, f, 0);
     if (lr < l0) return lmin + T(3) * (lr - l0);
-    const int lo = upper_bound_row<T, S>(p0, p1, f, lr, nf);
-    const T la = tload<T>(p0, lo) + f * (tload<T>(p1, lo) - tload<T>(p0, lo));
-    const T lb = tload<T>(p0, lo + 1) + f * (tload<T>(p1, lo + 1) - tload<T>(p0, lo + 1));
+    const int lo = upper_bound_row<T, S>(pp, f, lr, nf);
+    const T la = pair_value<T, S>(pp, f, lo);
+    const T lb = pair_value<T, S>(pp, f, lo + 1);
     const T inv = T(1) / static_cast<T>(nf - 1);
     const T xa = lmin * (T(1) - static_cast<T>(lo) * inv);
     const T xb = lmin * (T(1) - static_cast<T>(lo + 1) * inv);

@@ -24,6 +24,8 @@ void set_error(const std::string& msg);
 
 // Device view of one lookup table ("table view": non-owning pointers passed
 // by value to kernels).
+// The CDF arrays are in row-pair order: entry (n, k), n < n_chi - 1, holds
+// (P[n][k], P[n+1][k]) at [2 (n n_frac + k)] and [2 (n n_frac + k) + 1].
 struct TableDev {
     const double* ln_rate64;
     const double* cdf64;

@@ -45,7 +45,7 @@ namespace qedmi {
 constexpr unsigned long long kTrainStep = 0x5452414E494E4700ULL;   // draw stream of the training set
 
 // ------------------------------------------------------------ training set
-// Sample i: chi log-uniform over the trained range, u uniform over the
+// Sample i: chi log-uniform over the given range, u uniform over the
 // network's input domain, target from the FP64 table inverse CDF (Sec. 3.1 /
 // 3.2), weight (du/dy)^2 with y the sampled quantity in the network's output
 // units, so that the loss measures error in CDF space (the
@@ -486,8 +486,12 @@ extern "C" int32_t qed_surrogate_train(qed_context* ctx, const qed_table* table,
         return QED_ERR_ALLOC;
     }
     const SurrogateDev v = s->view();
+    // the training set reaches 1/16 of the log range beyond each end of the
+    // domain the network serves, so that its ends are fitted like its middle
+    const double ln_lo = std::log(cfg->chi_lo), ln_hi = std::log(cfg->chi_hi);
+    const double margin = (ln_hi - ln_lo) / 16.0;
     hipLaunchKernelGGL(surr_make_set, dim3(2048), dim3(256), 0, st, table->view(), v, cfg->seed, cfg->n_samples,
-                       std::log(cfg->chi_lo), std::log(cfg->chi_hi), set);
+                       ln_lo - margin, ln_hi + margin, set);
     e = hipGetLastError();
     double b1t = 1.0, b2t = 1.0;
     for (int it = 0; it < cfg->steps && e == hipSuccess; ++it) {

@@ -225,7 +225,18 @@ extern "C" int32_t qed_table_to_device(qed_table* t, void* stream) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) { set_error("hipGetDevice failed"); return QED_ERR_HIP; }
     free_device(t);
-    const size_t nr = t->ln_rate.size(), nc = t->cdf.size();
+    const size_t nr = t->ln_rate.size();
+    // CDF rows on the device in row-pair order: entry (n, k) holds
+    // (P[n][k], P[n+1][k]) side by side, n < n_chi - 1, so that the sampling
+    // search reads both rows it interpolates between with one load
+    const size_t nf = static_cast<size_t>(t->p.n_frac), npair = static_cast<size_t>(t->p.n_chi - 1);
+    const size_t nc = 2 * npair * nf;
+    std::vector<double> c64(nc);
+    for (size_t n = 0; n < npair; ++n)
+        for (size_t k = 0; k < nf; ++k) {
+            c64[2 * (n * nf + k)] = t->cdf[n * nf + k];
+            c64[2 * (n * nf + k) + 1] = t->cdf[(n + 1) * nf + k];
+        }
     std::vector<float> r32(nr), c32(nc);
     std::vector<uint16_t> c16(nc), r16(nr);
     for (size_t i = 0; i < nr; ++i) {
@@ -233,7 +244,7 @@ extern "C" int32_t qed_table_to_device(qed_table* t, void* stream) {
         r16[i] = to_bf16(r32[i]);
     }
     for (size_t i = 0; i < nc; ++i) {
-        c32[i] = static_cast<float>(t->cdf[i]);
+        c32[i] = static_cast<float>(c64[i]);
         c16[i] = to_bf16(c32[i]);
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -248,7 +259,7 @@ extern "C" int32_t qed_table_to_device(qed_table* t, void* stream) {
     t->device = dev;
     // pageable sources: hipMemcpyAsync stages them before returning
     if (hipMemcpyAsync(t->d_ln_rate64, t->ln_rate.data(), nr * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(t->d_cdf64, t->cdf.data(), nc * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(t->d_cdf64, c64.data(), nc * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(t->d_ln_rate32, r32.data(), nr * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(t->d_cdf32, c32.data(), nc * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(t->d_cdf16, c16.data(), nc * 2, hipMemcpyHostToDevice, s) != hipSuccess ||
