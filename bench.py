@@ -150,13 +150,18 @@ def run_path(Q, torch, ctx, tables, pops, dtype, steps, warmup, dt, chi_mode, se
     return res
 
 
+_ORACLE_TABLES = {}
+
+
 def cpu_baseline(pops_small, tables_params, dt, seed=1, min_seconds=10.0, max_steps=400):
     """The oracle, as it stands, on a bounded sample of the same workload."""
     from oracle import oracle as O
     n_chi, n_frac, rng = tables_params
-    log("cpu_baseline: generating oracle tables")
-    obw = O.Table(O.BW, rng[0], rng[1], n_chi, n_frac)
-    oqs = O.Table(O.QS, rng[0], rng[1], n_chi, n_frac)
+    key = (n_chi, n_frac, rng[0], rng[1])
+    if key not in _ORACLE_TABLES:
+        log("cpu_baseline: generating oracle tables")
+        _ORACLE_TABLES[key] = (O.Table(O.BW, rng[0], rng[1], n_chi, n_frac), O.Table(O.QS, rng[0], rng[1], n_chi, n_frac))
+    obw, oqs = _ORACLE_TABLES[key]
     el, ph = pops_small
     oe, og = O.Particles(el, O.ELECTRON, 0), O.Particles(ph, O.PHOTON, 1 << 40)
     O.init_optical_depth(oe, seed)
@@ -172,10 +177,35 @@ def cpu_baseline(pops_small, tables_params, dt, seed=1, min_seconds=10.0, max_st
         O.step(obw, oqs, og, dt, seed, steps, a2, a3)
         steps += 1
     wall = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = O.max_threads()
     return dict(value=steps * n / wall, unit="particle updates/s", cores=cores, kind="oracle",
+                cpu=cpu_model(),
                 sample=f"{oe.n} leptons + {og.n} photons of the same workload, {steps} steps "
                        f"(FP64 C oracle, OpenMP over particles, sequential append), {wall:.1f} s")
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline_one_thread(pops_small, tables_params, dt, seed=1, min_seconds=5.0):
+    """The same oracle on one thread (a smaller sample: per-update cost does
+    not depend on the population size)."""
+    from oracle import oracle as O
+    threads = O.max_threads()
+    O.set_threads(1)
+    try:
+        r = cpu_baseline(pops_small, tables_params, dt, seed, min_seconds=min_seconds)
+    finally:
+        O.set_threads(threads)
+    return r
 
 
 def fullstep(Q, torch, QI, args):
@@ -408,12 +438,16 @@ def main():
         rs = run_path(Q, torch, ctx, tables, pops, "f32", args.steps, args.warmup, dt, Q.CHI_FP64,
                       surrogates=(sb, sq))
         log(f"bench: FP32+surrogate {rs['updates_per_s']:.3e} upd/s, kernel {rs['kernel_ms_mean']:.3f} ms")
-    cpu = None
+    cpu = cpu1 = None
     if not args.no_cpu_baseline:
         m = 1 << args.cpu_sample_log2n
         small = tuple({k: v[:m] for k, v in p.items()} for p in pops)
         cpu = cpu_baseline(small, (256, 256, chi_range), dt)
         log(f"bench: oracle {cpu['value']:.3e} upd/s on {cpu['cores']} threads")
+        m1 = m >> 4
+        cpu1 = cpu_baseline_one_thread(tuple({k: v[:m1] for k, v in p.items()} for p in pops),
+                                       (256, 256, chi_range), dt)
+        log(f"bench: oracle {cpu1['value']:.3e} upd/s on {cpu1['cores']} thread")
 
     traffic = measured_traffic()
 
@@ -443,6 +477,7 @@ def main():
                      "alg_bytes_per_launch": r64["alg_bytes_per_launch"],
                      "hbm_bytes_per_launch": traffic.get("f64"), "kernel_digest": kernel_digest()},
         "cpu_baseline": cpu,
+        "cpu_baseline_one_thread": cpu1,
     }
     if r32 is not None:
         out["fp32_table_path"] = {

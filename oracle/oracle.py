@@ -94,6 +94,10 @@ def lib():
         L.orc_step.argtypes = [C.POINTER(_Table), C.POINTER(_Table), C.POINTER(_Particles), d, u64, u64,
                                d, d, _u8p, C.POINTER(_Append), C.POINTER(_Append)]
         L.orc_step.restype = C.c_int64
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
+        L.orc_max_threads.argtypes = []
+        L.orc_max_threads.restype = C.c_int
         L.orc_generate.argtypes = [C.POINTER(_Table), C.POINTER(_Table), C.POINTER(_Particles), _u8p,
                                    u64, u64, d, C.POINTER(_Append), C.POINTER(_Append)]
         L.orc_generate.restype = C.c_int64
@@ -335,6 +339,15 @@ class Append:
 
 def init_optical_depth(p: Particles, seed: int):
     lib().orc_init_optical_depth(p.cstruct, seed)
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def step(bw: Table, qs: Table, p: Particles, dt: float, seed: int, step_idx: int,

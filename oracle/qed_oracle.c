@@ -39,6 +39,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <quadmath.h>
+#include <omp.h>
 
 /* ------------------------------------------------------------------------ */
 /* Constants (CODATA 2018), paper Sec. 2: E_s = m_e^2 c^3 / (q_e hbar).     */
@@ -1082,3 +1083,10 @@ void orc_push(orc_particles* p, double* x, double* y, double* z, const orc_field
         x[i] = r[0]; y[i] = r[1]; z[i] = r[2];
     }
 }
+
+/* Threads of the OpenMP loops (baseline timing at one and at all threads). */
+void orc_set_threads(int n) {
+    if (n > 0) omp_set_num_threads(n);
+}
+
+int orc_max_threads(void) { return omp_get_max_threads(); }

@@ -284,8 +284,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 for (int b = 0; b < kBatch; ++b) {
                     const int loc = (it + b) * kBlock + tid;
                     const int64_t j = c.begin + (loc < c.len ? loc : 0);
+                    // u with ordinary loads (phase 2b gathers the events' u
+                    // again, and finds many of its lines still cached), the
+                    // fields and tau non-temporal (read once)
 #pragma unroll
-                    for (int q = 0; q < 10; ++q) v[b][q] = ldnt<T>(S.p[q], j);
+                    for (int q = 0; q < 10; ++q) v[b][q] = q < 3 ? ld<T>(S.p[q], j) : ldnt<T>(S.p[q], j);
                     // caller units -> u = p/(m_e c), V/m, T (factors 1 for SI)
 #pragma unroll
                     for (int q = 0; q < 9; ++q)

@@ -241,13 +241,17 @@ def test_bit_identical_rerun(ctx, tabs):
         np.testing.assert_array_equal(a, b)
 
 
-def test_standalone_generate_matches_oracle(ctx, tabs):
+@pytest.mark.parametrize("every", [3, 1, 2])
+def test_standalone_generate_matches_oracle(ctx, tabs, every):
+    """Flagged particles produce: one in three (a chunk's optical depths all
+    fit the free LDS slots but the last), all (none fit: every event draws
+    again in the write phase) and one in two (half fit)."""
     (bw, qs), (obw, oqs) = tabs
     n = 9000
     for photon in (False, True):
         pop = QI.plane_wave_counter(n, 10, photon, stream=int(photon))
         sp = O.PHOTON if photon else O.ELECTRON
-        flags = (np.arange(n) % 3 == 0).astype(np.uint8)
+        flags = (np.arange(n) % every == 0).astype(np.uint8)
         op = O.Particles(pop, sp, id_base=777)
         O.init_optical_depth(op, 10)
         d = dev_pop(pop, torch.float64, tau=op["tau"])
