@@ -115,8 +115,12 @@ int32_t qed_table_load(const char* path, qed_table** out);
 int32_t qed_table_host_data(const qed_table* t, const double** ln_rate, const double** cdf,
                             qed_table_params* params);
 
-/* Copy the table to the current device in FP64, FP32 and BF16 (the BF16
- * copy holds the CDF only, for precision studies).  Asynchronous on stream. */
+/* Copy the table to the current device in FP64, FP32 and BF16 (BF16 for
+ * precision studies).  The device CDF is stored in row-pair order: entry
+ * (n, m), n < n_chi - 1, holds cdf[n][m] and cdf[n+1][m] side by side, so
+ * that a sampling probe reads both rows it interpolates between with one
+ * load ((n_chi - 1) x n_frac pairs).  Returns after the copies are done (the
+ * converted copies are staged in host memory owned by the call). */
 int32_t qed_table_to_device(qed_table* t, void* stream);
 
 void qed_table_destroy(qed_table* t);
