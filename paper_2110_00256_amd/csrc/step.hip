@@ -71,9 +71,9 @@ __device__ __forceinline__ unsigned bits_below(unsigned long long mask) {
                                      __builtin_amdgcn_mbcnt_lo(static_cast<unsigned>(mask), 0u));
 }
 
-// Decoupled look-back (Merrill & Garland 2016), in two halves called by one
-// thread: publish() posts the chunk's aggregate as soon as it is known,
-// resolve() later returns the exclusive prefix over earlier chunks of the
+// Decoupled look-back (Merrill & Garland 2016), in two halves: publish()
+// (one thread) posts the chunk's aggregate as soon as it is known, resolve()
+// (one wave) later returns the exclusive prefix over earlier chunks of the
 // same product stream and posts the inclusive one.  A status word carries
 // the launch epoch, the flag and the value together, so relaxed
 // device-scope atomics are enough: no other data is published through it.
@@ -85,29 +85,68 @@ __device__ __forceinline__ void publish(const StepArgs& a, int k, const ChunkDes
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// resolve() is done by a whole wave: lane l polls chunk base - l, so a
+// window of 64 predecessors costs one round of loads.  The nearest
+// predecessor holding an inclusive prefix (flag P) ends the walk; every
+// chunk between it and k must have posted at least its aggregate, else the
+// window is polled again.  Chunks before the stream's first count as P with
+// value 0.  Returns the exclusive prefix in every lane; lane 0 posts the
+// inclusive one.
 __device__ long long resolve(const StepArgs& a, int k, const ChunkDesc& c, unsigned long long agg, int64_t* err) {
-    if (k == c.stream_first) return 0;
+    const int lane = static_cast<int>(lane_id());
     long long excl = 0;
-    int j = k - 1;
-    int spins = 0;
-    while (j >= c.stream_first) {
-        const unsigned long long v =
-            __hip_atomic_load(a.status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned flag = static_cast<unsigned>(v >> 30) & 3u;
-        if (static_cast<uint32_t>(v >> 32) != a.epoch || flag == 0u) {
-            if (++spins > kSpinLimit) {   // predecessor never published: give up, report
-                if (err) atomicAdd(reinterpret_cast<unsigned long long*>(err), 1ULL);
-                break;
+    if (k != c.stream_first) {
+        int base = k - 1;
+        int spins = 0;
+        // the nearest predecessor is the one most often still running: wait
+        // for it with a single lane polling; if it holds its inclusive
+        // prefix the walk ends there, else whole windows are read
+        unsigned long long v0 = 0;
+        if (lane == 0) {
+            for (;;) {
+                v0 = __hip_atomic_load(a.status + base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (static_cast<uint32_t>(v0 >> 32) == a.epoch && ((v0 >> 30) & 3u) != 0u) break;
+                if (++spins > kSpinLimit) break;
+                __builtin_amdgcn_s_sleep(1);
             }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
         }
-        excl += static_cast<long long>(v & kValueMask);
-        if (flag == kFlagP) break;
-        --j;
+        spins = __shfl(spins, 0);
+        v0 = __shfl(v0, 0);
+        const bool done = static_cast<uint32_t>(v0 >> 32) == a.epoch && ((v0 >> 30) & 3u) == kFlagP;
+        if (done) excl = static_cast<long long>(v0 & kValueMask);
+        while (!done) {
+            const int j = base - lane;
+            unsigned flag = kFlagP;
+            long long val = 0;
+            if (j >= c.stream_first) {
+                const unsigned long long v =
+                    __hip_atomic_load(a.status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                flag = static_cast<uint32_t>(v >> 32) == a.epoch ? (static_cast<unsigned>(v >> 30) & 3u) : 0u;
+                val = static_cast<long long>(v & kValueMask);
+            }
+            const unsigned long long pmask = __ballot(flag == kFlagP);
+            const unsigned long long xmask = __ballot(flag == 0u);
+            const int p = pmask ? __builtin_ctzll(pmask) : 64;   // nearest P, 64: none in the window
+            const unsigned long long upto = p >= 63 ? ~0ULL : ((2ULL << p) - 1ULL);
+            if (xmask & upto) {                                    // a chunk on the way has not posted
+                if (++spins > kSpinLimit) {   // predecessor never published: give up, report
+                    if (err && lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(err), 1ULL);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            long long part = lane <= p ? val : 0;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+            excl += part;
+            if (p < 64) break;
+            base -= 64;
+        }
     }
-    __hip_atomic_store(a.status + k, pack_status(a.epoch, kFlagP, static_cast<unsigned long long>(excl) + agg),
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0)
+        __hip_atomic_store(a.status + k, pack_status(a.epoch, kFlagP, static_cast<unsigned long long>(excl) + agg),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return excl;
 }
 
@@ -463,9 +502,12 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
         const int prods = thresh ? s_kept : total;
 
         // ---------------- decoupled look-back over the chunk's stream
+        if (wave == 0) {
+            const long long excl = resolve(a, k, c, static_cast<unsigned long long>(prods),
+                                           a.stats ? a.stats + QED_STAT_SCAN_TIMEOUT : nullptr);
+            if (lane == 0) s_excl = excl;
+        }
         if (tid == 0) {
-            s_excl = resolve(a, k, c, static_cast<unsigned long long>(prods),
-                             a.stats ? a.stats + QED_STAT_SCAN_TIMEOUT : nullptr);
             const long long incl = s_excl + prods;
             if (k == c.stream_last) {
                 if (photon) {
