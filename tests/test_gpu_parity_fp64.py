@@ -200,6 +200,43 @@ def test_tiles_follow_tile_order(ctx, tabs):
     _run_steps(ctx, tabs, n, n, 2, seed=4, tiles=tiles)
 
 
+def test_tiles_with_odd_boundaries(ctx, tabs):
+    """Tiles starting at odd indices (the streaming phase falls back from
+    16-byte loads to one element per load) and ragged tile ends."""
+    n = 20000
+    tiles = [(0, 1, 7001), (1, 3, 20000), (0, 7001, 20000), (0, 0, 1), (1, 0, 3)]
+    _run_steps(ctx, tabs, n, n, 2, seed=14, tiles=tiles)
+
+
+def test_unaligned_arrays(ctx, tabs):
+    """Particle arrays that are views one element into their allocation
+    (not 16-byte aligned): same results as the oracle."""
+    (bw, qs), (obw, oqs) = tabs
+    n, seed = 9001, 15
+    el, _ = QI.c1_population(seed=seed, n=n)
+    oe = O.Particles(el, O.ELECTRON, id_base=0)
+    O.init_optical_depth(oe, seed)
+    full = {k: torch.zeros(n + 1, dtype=torch.float64, device="cuda") for k in list(el) + ["tau"]}
+    d = {k: v[1:] for k, v in full.items()}
+    for k in el:
+        d[k].copy_(torch.as_tensor(el[k]))
+    d["tau"].copy_(torch.as_tensor(oe["tau"]))
+    pe = Q.particles(d, Q.ELECTRON, 0)
+    ph_b = Q.AppendBuffer(n, torch.float64)
+    desc = Q.StepDesc([pe], bw=bw, qs=qs, photons=ph_b, electrons=Q.AppendBuffer(0, torch.float64),
+                      positrons=Q.AppendBuffer(0, torch.float64), dt=1e-16, seed=seed)
+    o_ph = O.Append(n)
+    u0 = np.sqrt(oe["ux"] ** 2 + oe["uy"] ** 2 + oe["uz"] ** 2)
+    Q.step(ctx, desc)
+    O.step(obw, oqs, oe, 1e-16, seed, 0, o_ph)
+    torch.cuda.synchronize()
+    assert o_ph.count > 100
+    compare_append(ph_b, o_ph, RTOL, "photons", u0[o_ph.parent[:o_ph.count]])
+    assert rel_close(host(d["tau"]), oe["tau"], RTOL) <= 1.0
+    for k in ("ux", "uy", "uz"):
+        assert rel_close(host(d[k]), oe[k], RTOL, floor=np.maximum(u0, 1e-300)) <= 1.0
+
+
 def test_photon_threshold(ctx, tabs):
     ev, (ph_b, _, _), (o_ph, _, _) = _run_steps(ctx, tabs, 30000, 10, 3, seed=5, threshold=2.0)
     assert 0 < o_ph.count < ev
