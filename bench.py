@@ -30,7 +30,8 @@ if ROOT not in sys.path:
 METRIC = "QED particle updates/s at 1 MI355X (FP64 table vs FP32+surrogate), % HBM peak"
 HBM_PEAK_GBS = 8000.0
 
-# algorithmic bytes: per update, and extra per event
+# algorithmic bytes per particle update (u, E, B, tau read; tau written) and extra per
+# event (parent u written, w read, product records)
 BYTES = {
     "f64": dict(base=88, qs_event=80, bw_event=104),
     "f32": dict(base=44, qs_event=44, bw_event=60),
@@ -40,7 +41,7 @@ BYTES = {
 # HBM bytes per launch measured with rocprofv3 (FETCH_SIZE, WRITE_SIZE, each
 # calibrated on a plain copy) live in this summary, tagged with a digest of
 # the step kernel's sources; they are reported only while the digest matches.
-PROFILE = os.path.join(ROOT, "profiles", "step_kernel_cone_c2.md")
+PROFILE = os.path.join(ROOT, "profiles", "step_kernel_cone_2x2e24.md")
 KERNEL_SOURCES = ("step.hip", "device_physics.hpp", "internal.hpp", "surrogate.hpp", "constants.hpp")
 
 
@@ -213,7 +214,7 @@ def fullstep(Q, torch, QI, args):
     1024 lognormal tiles per species interleaved, FP32 fields of a focused
     Gaussian pulse, dt for 1% events; one persistent launch per step."""
     n = 1 << (args.log2n + 1)
-    dt = json.load(open(os.path.join(ROOT, "tests", "golden", "c5_dt.json")))["dt_s"]
+    dt = json.load(open(os.path.join(ROOT, "tests", "golden", "fullstep_dt.json")))["dt_s"]
     log(f"fullstep: generating 4 x {n} particles and 4096 tiles")
     pops = QI.fullstep_population(n, seed=1)
     tiles = QI.fullstep_layout(n, 1024, seed=1)
@@ -413,7 +414,7 @@ def main():
     dt = 1e-16
     chi_range = (1e-4, 1e3)
     log(f"bench: generating inputs 2^{args.log2n} leptons + 2^{args.log2n} photons")
-    pops = QI.c2_population(seed=1, n=n)
+    pops = QI.cone_population(seed=1, n=n)
     ctx = Q.Context(0)
     log("bench: generating 256x256 tables")
     tables = make_tables(Q, 256, 256, chi_range)

@@ -1,7 +1,7 @@
 """Derive the time step of the full-step workload (4 species in lognormal
 tiles, focused Gaussian pulse) so that the mean per-step event fraction of
 the QED-active particles is 1%, using the oracle's rates on a 2^20-particle
-subsample.  Writes tests/golden/c5_dt.json.  Run: python oracle/derive_c5_dt.py"""
+subsample.  Writes tests/golden/fullstep_dt.json.  Run: python oracle/derive_fullstep_dt.py"""
 import json
 import math
 import os
@@ -47,7 +47,7 @@ def main():
     out = {"dt_s": dt, "event_fraction": frac(dt), "target": TARGET, "subsample": n,
            "recipe": "qed_inputs.gaussian_pulse, seed 1, streams 0/1/2 for e-/e+/photons, FP32 inputs; "
                      "oracle 256-point rate tables over chi [1e-4, 1e4]; mean of 1 - exp(-rate dt)"}
-    path = os.path.join(ROOT, "tests", "golden", "c5_dt.json")
+    path = os.path.join(ROOT, "tests", "golden", "fullstep_dt.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))

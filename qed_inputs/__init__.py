@@ -171,13 +171,13 @@ def gaussian_pulse(n: int, seed: int, photon: bool, stream: int = 0,
     return _pack(ux, uy, uz, z, ey, z, z, z, bz, w, dtype)
 
 
-def c1_population(seed: int = 1, n: int = 1 << 16, dtype=np.float64):
+def parity_population(seed: int = 1, n: int = 1 << 16, dtype=np.float64):
     """Parity workload: n electrons + n photons, a0 = 100 plane wave."""
     return (plane_wave_counter(n, seed, photon=False, stream=0, dtype=dtype),
             plane_wave_counter(n, seed, photon=True, stream=1, dtype=dtype))
 
 
-def c2_population(seed: int = 1, n: int = 1 << 24, dtype=np.float64):
+def cone_population(seed: int = 1, n: int = 1 << 24, dtype=np.float64):
     """Roofline workload: n leptons + n photons in a 0.1 rad cone."""
     return (plane_wave_cone(n, seed, photon=False, stream=0, dtype=dtype),
             plane_wave_cone(n, seed, photon=True, stream=1, dtype=dtype))

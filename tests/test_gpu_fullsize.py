@@ -39,7 +39,7 @@ def test_bench_size_fp64_step_matches_oracle(ctx):
     (bw, qs) = lib_tables(RANGE, RANGE, 256, 256)
     (obw, oqs) = oracle_tables(RANGE, RANGE, 256, 256)
     print("population 2^24 + 2^24", flush=True)
-    el, ph = QI.c2_population(seed=SEED, n=N)
+    el, ph = QI.cone_population(seed=SEED, n=N)
     oe, og = O.Particles(el, O.ELECTRON, id_base=0), O.Particles(ph, O.PHOTON, id_base=N)
     O.init_optical_depth(oe, SEED)
     O.init_optical_depth(og, SEED)

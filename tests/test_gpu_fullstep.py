@@ -17,7 +17,7 @@ import paper_2110_00256_amd as Q  # noqa: E402
 import qed_inputs as QI  # noqa: E402
 from oracle import oracle as O  # noqa: E402
 
-GOLD = os.path.join(os.path.dirname(__file__), "golden", "c5_dt.json")
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "fullstep_dt.json")
 
 
 @pytest.fixture(scope="module")

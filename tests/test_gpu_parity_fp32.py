@@ -62,7 +62,7 @@ def _check_products(g_arrays, g_parent, o_app, ok_parents, what, parent_umag):
 def test_fp32_stepwise(ctx, tabs, chi_mode):
     (bw, qs), (obw, oqs) = tabs
     n = 1 << 16
-    el, ph = QI.c2_population(seed=21, n=n)
+    el, ph = QI.cone_population(seed=21, n=n)
     dt = 1e-16
     d_e = {k: torch.as_tensor(v).to("cuda", torch.float32) for k, v in el.items()}
     d_g = {k: torch.as_tensor(v).to("cuda", torch.float32) for k, v in ph.items()}

@@ -87,7 +87,7 @@ def _run_steps(ctx, tabs, n_e, n_g, steps, seed=1, dt=1e-16, threshold=0.0, cap=
                check_each_step=True, chi_qed_min=0.0):
     """Run the fused step on GPU and the oracle side by side; compare."""
     (bw, qs), (obw, oqs) = tabs
-    el, ph = QI.c1_population(seed=seed, n=max(n_e, n_g))
+    el, ph = QI.parity_population(seed=seed, n=max(n_e, n_g))
     el = {k: v[:n_e] for k, v in el.items()}
     ph = {k: v[:n_g] for k, v in ph.items()}
     oe, og = O.Particles(el, O.ELECTRON, id_base=0), O.Particles(ph, O.PHOTON, id_base=1 << 40)
@@ -181,7 +181,7 @@ def _oracle_tiles(obw, oqs, osets, tiles, dt, seed, s, o_ph, o_el, o_po, thresho
     return ev
 
 
-def test_c1_fused_step_ten_steps(ctx, tabs):
+def test_parity_workload_ten_steps(ctx, tabs):
     """The parity workload: 2^16 electrons + 2^16 photons, 10 steps."""
     ev, _, _ = _run_steps(ctx, tabs, 1 << 16, 1 << 16, 10)
     assert ev > 1000
@@ -213,7 +213,7 @@ def test_unaligned_arrays(ctx, tabs):
     (not 16-byte aligned): same results as the oracle."""
     (bw, qs), (obw, oqs) = tabs
     n, seed = 9001, 15
-    el, _ = QI.c1_population(seed=seed, n=n)
+    el, _ = QI.parity_population(seed=seed, n=n)
     oe = O.Particles(el, O.ELECTRON, id_base=0)
     O.init_optical_depth(oe, seed)
     full = {k: torch.zeros(n + 1, dtype=torch.float64, device="cuda") for k in list(el) + ["tau"]}
@@ -258,7 +258,7 @@ def test_capacity_overflow_counts_and_prefix(ctx, tabs):
 
 def test_bit_identical_rerun(ctx, tabs):
     (bw, qs), _ = tabs
-    el, ph = QI.c1_population(seed=9, n=30000)
+    el, ph = QI.parity_population(seed=9, n=30000)
     outs = []
     for _ in range(2):
         de, dg = dev_pop(el, torch.float64), dev_pop(ph, torch.float64)

@@ -67,7 +67,7 @@ def ctx():
 
 @pytest.fixture(scope="module")
 def cone():
-    return QI.c2_population(seed=SEED, n=N, dtype=np.float32)
+    return QI.cone_population(seed=SEED, n=N, dtype=np.float32)
 
 
 @pytest.fixture(scope="module")
@@ -118,7 +118,7 @@ def test_chi_precision_counterpropagating(ctx, cone):
             # output rounding + cancellation-amplified arithmetic error
             if not np.all(err <= 1.01 * U32 + 64 * unit * kappa):
                 bad.append(f"{name} {mname}")
-    report("chi_cone_c2", res)
+    report("chi_cone", res)
     assert not bad, bad
 
 
@@ -177,7 +177,7 @@ def test_table_precision(ctx, cone, tabs):
             else:
                 res[f"{name}/lnxi_abs/{store}"] = dist(np.abs(xi - ref_xi))
         res[f"{name}/live_rate_fraction"] = float(live.mean())
-    report("tables_c2_256", res)
+    report("tables_cone_256", res)
     # FP32 storage + FP32 arithmetic: ln-rate interpolation error of a few
     # FP32 ulps of |ln rate| (<= ~40 here), through exp
     assert res["qs/rate/fp32"]["max"] < 2e-4 and res["bw/rate/fp32"]["max"] < 2e-4
@@ -251,7 +251,7 @@ def test_step_precision(ctx, cone, tabs, chi_mode):
                                                    np.maximum(oa["tau"][oi], 1.0))
             res[f"{name}/{pname}_count"] = [ng, int(oa.count)]
     mname = "fp64" if chi_mode == Q.CHI_FP64 else "comp32"
-    report(f"step_c2_fp32_chi_{mname}", res)
+    report(f"step_cone_fp32_chi_{mname}", res)
     assert far_flips == 0, "event flip away from tau = 0"
     # The FP32 path rounds the uniform of the sampling draw to FP32: near
     # r -> 1 (the hardest photons, where ln P is flat) the FP32 spacing 6e-8

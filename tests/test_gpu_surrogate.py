@@ -162,7 +162,7 @@ def test_step_with_surrogate_probe_and_counts(ctx, tables):
     cfg_b0 = Q.Surrogate.cfg(Q.BW, 1e-3, 1e3, probe_tol=0.0, probe_every=1)
     sq0 = Q.Surrogate.from_host(qs, cfg_q0, sq.params())
     sb0 = Q.Surrogate.from_host(bw, cfg_b0, sb.params())
-    el, ph = QI.c2_population(seed=8, n=1 << 18)
+    el, ph = QI.cone_population(seed=8, n=1 << 18)
     results = {}
     for name, surr in (("table", (None, None)), ("probe0", (sb0, sq0)), ("surr", (sb, sq))):
         d = []

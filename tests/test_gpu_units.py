@@ -40,7 +40,7 @@ def test_step_in_unit_system(ctx, tabs, system, ref):
     (bw, qs), (obw, oqs) = tabs
     n, seed, dt_si, steps = 20000, 13, 1e-16, 3
     f = U.factors(system, ref)
-    el, ph = QI.c1_population(seed=seed, n=n)
+    el, ph = QI.parity_population(seed=seed, n=n)
     oe, og = O.Particles(el, O.ELECTRON, 0), O.Particles(ph, O.PHOTON, n)
     O.init_optical_depth(oe, seed)
     O.init_optical_depth(og, seed)

@@ -148,7 +148,7 @@ def test_event_fraction_matches_total_rate(tables64, photon):
 
 def test_step_kinematics_conservation_and_order(tables64):
     bw, qs = tables64
-    el, ph = QI.c1_population(seed=1, n=1 << 12)
+    el, ph = QI.parity_population(seed=1, n=1 << 12)
     for pop, sp in ((el, O.ELECTRON), (ph, O.PHOTON)):
         p = O.Particles(pop, sp, id_base=77)
         O.init_optical_depth(p, seed=1)
@@ -209,7 +209,7 @@ def test_init_optical_depth_keying():
 
 def test_capacity_and_threshold(tables64):
     bw, qs = tables64
-    el, _ = QI.c1_population(seed=2, n=1 << 12)
+    el, _ = QI.parity_population(seed=2, n=1 << 12)
     ref = O.Particles(el, O.ELECTRON)
     O.init_optical_depth(ref, seed=2)
     small = O.Particles(el, O.ELECTRON, tau=ref["tau"])
