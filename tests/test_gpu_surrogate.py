@@ -207,12 +207,14 @@ def test_step_with_surrogate_probe_and_counts(ctx, tables):
 
 
 def test_gain_over_table(ctx, tables512, trained):
-    """What the network buys over the table: sampling time for 2^24 events
+    """What the network buys over the table: sampling time for 2^26 events
     with chi log-uniform over the trained range plus 2^16 out-of-range
     events (which fall back to the table), both kernels timed with HIP
-    events on the launch stream; the fallback events match the table bit for
-    bit."""
-    n_in, n_out = 1 << 24, 1 << 16
+    events on the launch stream, and the memory each needs; the fallback
+    events match the table bit for bit.  The times are reported, not
+    asserted: with 512 x 512 FP32 tables resident in L2 the table search is
+    the faster of the two on this hardware."""
+    n_in, n_out = 1 << 26, 1 << 16
     for proc in (Q.QS, Q.BW):
         table = tables512[0] if proc == Q.BW else tables512[1]
         s, _ = trained[proc]
@@ -235,6 +237,7 @@ def test_gain_over_table(ctx, tables512, trained):
         np.testing.assert_array_equal(a[n_in:].cpu().numpy(), b[n_in:].cpu().numpy())
         tp = table.host_data()[0]
         print(f"process {proc}: table {times['table']:.3f} ms, surrogate {times['surrogate']:.3f} ms "
-              f"for {n_in + n_out} events (gain x{times['table'] / times['surrogate']:.2f}); "
+              f"for {n_in + n_out} events, {n_out / (n_in + n_out):.2e} of them out of range "
+              f"(gain x{times['table'] / times['surrogate']:.2f}); "
               f"table {4 * tp.n_chi * (tp.n_frac + 1)} B in FP32, network {4 * 4417 + 2 * 4096} B")
         assert times["surrogate"] > 0 and times["table"] > 0
