@@ -284,8 +284,19 @@ __global__ void __launch_bounds__(256) surr_update_kernel(float* params, float* 
                                                           float* loss_out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i > kNParam) return;
+    // the partials are added in wave order (deterministic); loads go out 64
+    // at a time so that one memory latency covers 64 of them
+    constexpr int kGroup = 64;
     float g = 0.f;
-    for (int w = 0; w < n_waves; ++w) g += part[static_cast<size_t>(w) * (kNParam + 1) + i];
+    int w = 0;
+    for (; w + kGroup <= n_waves; w += kGroup) {
+        float t[kGroup];
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) t[q] = part[static_cast<size_t>(w + q) * (kNParam + 1) + i];
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) g += t[q];
+    }
+    for (; w < n_waves; ++w) g += part[static_cast<size_t>(w) * (kNParam + 1) + i];
     if (i == kNParam) {
         if (loss_out) *loss_out = g;
         return;
