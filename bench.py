@@ -371,6 +371,9 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--log2n", type=int, default=24, help="particles per species = 2^log2n")
+    ap.add_argument("--dt", type=float, default=1e-16,
+                    help="time step of the cone workload in s (1e-16: 31%% lepton events per step; "
+                         "5.5e-18: about 1%% of all particles)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-steps", type=int, default=320000)
@@ -411,7 +414,7 @@ def main():
         return
 
     n = 1 << args.log2n
-    dt = 1e-16
+    dt = args.dt
     chi_range = (1e-4, 1e3)
     log(f"bench: generating inputs 2^{args.log2n} leptons + 2^{args.log2n} photons")
     pops = QI.cone_population(seed=1, n=n)
@@ -468,8 +471,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "cone plane wave: 2^24 leptons + 2^24 photons, 256x256 tables over chi "
-                               "[1e-4, 1e3], dt 0.1 fs, FP64 table path",
+        "config": {"workload": f"cone plane wave: 2^{args.log2n} leptons + 2^{args.log2n} photons, 256x256 "
+                               f"tables over chi [1e-4, 1e3], dt {dt:g} s, FP64 table path",
                    "particles": 2 * n, "dt_s": dt, "table": "256x256",
                    "qs_event_fraction": r64["qs_event_fraction"], "bw_event_fraction": r64["bw_event_fraction"]},
         "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
