@@ -453,7 +453,8 @@ def main():
                                        (256, 256, chi_range), dt)
         log(f"bench: oracle {cpu1['value']:.3e} upd/s on {cpu1['cores']} thread")
 
-    traffic = measured_traffic()
+    # the profile was taken on the default workload (2^24 + 2^24, dt 1e-16 s)
+    traffic = measured_traffic() if (args.log2n == 24 and args.dt == 1e-16) else {}
 
     def traffic_gbs(key, r):
         return traffic[key] / (r["kernel_ms_mean"] * 1e-3) / 1e9 if key in traffic else None
