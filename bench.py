@@ -365,6 +365,63 @@ def paper(Q, torch, QI, args):
     print(json.dumps(out), flush=True)
 
 
+def extras(Q, torch, QI, args):
+    """Throughput of the library's other kernels (one JSON line): the
+    Schwinger rate and pair count over 2^26 cells (fields uniform in
+    +-E_s/10, +-E_s/(10c)), and the Boris push of 2^25 electrons through a
+    circularly polarised wave (E0 = 1.22e-4 E_s, 0.8 um), FP64, HIP events on
+    the launch stream, mean of 10 calls after one warm-up."""
+    ctx = Q.Context(0)
+    out = {"workload": "extras: Schwinger rate/pairs on 2^26 cells, push of 2^25 electrons, FP64"}
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    n = 1 << 26
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    es = QI.E_SCHWINGER
+    d = {k: (torch.rand(n, generator=g, device="cuda", dtype=torch.float64) * 2 - 1) * es / 10 *
+         (1.0 if k[0] == "e" else 1.0 / QI.C_LIGHT) for k in ("ex", "ey", "ez", "bx", "by", "bz")}
+    c = Q.cells(d)
+    rate = torch.empty(n, dtype=torch.float64, device="cuda")
+    ms = timed(lambda: Q.schwinger_rate(ctx, c, rate))
+    out["schwinger_rate"] = {"cells": n, "ms": ms, "cells_per_s": n / (ms * 1e-3),
+                             "achieved_gbs": 56 * n / (ms * 1e-3) / 1e9}
+    # cell volume 1e-28 m^3 and dt 1e-18 s: about 3e5 pairs from these fields
+    el, po = Q.AppendBuffer(1 << 21, torch.float64), Q.AppendBuffer(1 << 21, torch.float64)
+
+    def pairs():
+        el.reset()
+        po.reset()
+        Q.schwinger_pairs(ctx, c, 1e-28, 1e-18, 1.0, 1, 0, el, po)
+    ms = timed(pairs)
+    out["schwinger_pairs"] = {"cells": n, "ms": ms, "cells_per_s": n / (ms * 1e-3), "pairs": int(el.count.item())}
+    del d, c, rate
+    m = 1 << 25
+    um = 4120.0
+    pe = {k: torch.zeros(m, dtype=torch.float64, device="cuda") for k in QI.FIELDS}
+    pe["ux"].fill_(-um)
+    pe["tau"] = torch.ones(m, dtype=torch.float64, device="cuda")
+    x = torch.rand(m, generator=g, device="cuda", dtype=torch.float64) * 0.8e-6
+    y, z = torch.zeros_like(x), torch.zeros_like(x)
+    pp = Q.particles(pe, Q.ELECTRON, 0)
+    f = Q.cp_wave(1.22e-4 * es, 0.8e-6, 1)
+    ms = timed(lambda: Q.push(ctx, pp, x, y, z, f, 0.0, 3e-17))
+    # read u and x, y, z; write u, x, y, z and the six field components
+    out["push"] = {"particles": m, "ms": ms, "particles_per_s": m / (ms * 1e-3),
+                   "achieved_gbs": 144 * m / (ms * 1e-3) / 1e9}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -382,7 +439,7 @@ def main():
                     help="the oracle is timed on the first 2^k particles of each species, whole steps, >= 10 s")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
-    ap.add_argument("--workload", choices=("cone", "fullstep", "paper"), default="cone",
+    ap.add_argument("--workload", choices=("cone", "fullstep", "paper", "extras"), default="cone",
                     help="cone: the default roofline workload; fullstep: 4 species in lognormal tiles, "
                          "Gaussian pulse, FP32 table and FP32+surrogate paths; paper: the paper's own "
                          "benchmark of the four standalone calls")
@@ -411,6 +468,9 @@ def main():
         return
     if args.workload == "paper":
         paper(Q, torch, QI, args)
+        return
+    if args.workload == "extras":
+        extras(Q, torch, QI, args)
         return
 
     n = 1 << args.log2n

@@ -187,15 +187,23 @@ __device__ __forceinline__ void put(const AppendDev& o, int64_t slot, T w, T tau
 // range, so a block-wide exclusive scan of the thread totals orders the
 // pairs by cell.  base_e / base_p: the buffers' counts before this call
 // (count - total after the scan kernel).
+// The counts are computed with consecutive lanes on consecutive cells
+// (coalesced field loads) into LDS, then each thread takes its own cells'.
 template <typename T>
 __global__ void __launch_bounds__(kSwBlock) sw_write_kernel(SwArgs a) {
     __shared__ int64_t lds[kSwBlock / 64];
-    const int64_t first = static_cast<int64_t>(blockIdx.x) * kSwCells + threadIdx.x * kSwPerThread;
+    __shared__ int64_t cnt[kSwCells];
+    const int64_t bfirst = static_cast<int64_t>(blockIdx.x) * kSwCells;
+    for (int q = 0; q < kSwPerThread; ++q) {
+        const int64_t i = bfirst + q * kSwBlock + threadIdx.x;
+        cnt[q * kSwBlock + threadIdx.x] = i < a.n ? cell_pairs<T>(a, i) : 0;
+    }
+    __syncthreads();
+    const int64_t first = bfirst + threadIdx.x * kSwPerThread;
     int64_t k[kSwPerThread];
     int64_t v = 0;
     for (int q = 0; q < kSwPerThread; ++q) {
-        const int64_t i = first + q;
-        k[q] = i < a.n ? cell_pairs<T>(a, i) : 0;
+        k[q] = cnt[threadIdx.x * kSwPerThread + q];
         v += k[q];
     }
     int64_t tot;
