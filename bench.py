@@ -370,7 +370,9 @@ def extras(Q, torch, QI, args):
     Schwinger rate and pair count over 2^26 cells (fields uniform in
     +-E_s/10, +-E_s/(10c)), and the Boris push of 2^25 electrons through a
     circularly polarised wave (E0 = 1.22e-4 E_s, 0.8 um), FP64, HIP events on
-    the launch stream, mean of 10 calls after one warm-up."""
+    the launch stream, mean of 10 calls after one warm-up; and the device
+    table generation (256 x 256 and 512 x 512 over chi in [1e-4, 1e3], wall
+    time of the synchronous call after one warm-up)."""
     ctx = Q.Context(0)
     out = {"workload": "extras: Schwinger rate/pairs on 2^26 cells, push of 2^25 electrons, FP64"}
 
@@ -419,6 +421,16 @@ def extras(Q, torch, QI, args):
     # read u and x, y, z; write u, x, y, z and the six field components
     out["push"] = {"particles": m, "ms": ms, "particles_per_s": m / (ms * 1e-3),
                    "achieved_gbs": 144 * m / (ms * 1e-3) / 1e9}
+    # table generation on the device (FP64 quadrature), synchronous calls
+    tg = {}
+    for nn in (256, 512):
+        for name, proc in (("bw", Q.BW), ("qs", Q.QS)):
+            Q.Table.generate_device(proc, 1e-4, 1e3, nn, nn)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Q.Table.generate_device(proc, 1e-4, 1e3, nn, nn)
+            tg[f"{name}_{nn}x{nn}_ms"] = (time.perf_counter() - t0) * 1e3
+    out["table_generation_device"] = tg
     print(json.dumps(out), flush=True)
 
 
