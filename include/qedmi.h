@@ -393,7 +393,9 @@ int32_t qed_schwinger_rate(qed_context* ctx, const qed_cells* cells, void* rate_
  * 2(i%2)+1 of pair i).  The counts are incremented on the device; capacity
  * contract as for qed_step (pairs beyond capacity are not written; check
  * with qed_read_count).  Buffers must have dtype = cells->dtype.
- * cell_volume in m^3, dt in s, weight = physical pairs per macro-pair > 0. */
+ * cell_volume in m^3, dt in s, weight = physical pairs per macro-pair > 0.
+ * The context keeps 8 bytes of device scratch per cell of the largest call
+ * (each cell's count, computed once and used to place the pairs). */
 int32_t qed_schwinger_pairs(qed_context* ctx, const qed_cells* cells, double cell_volume, double dt,
                             double weight, uint64_t seed, uint64_t step, qed_append* electrons,
                             qed_append* positrons, void* stream);

@@ -47,6 +47,7 @@ struct SwArgs {
     int64_t* bsum;        // per-block pair totals, then exclusive offsets
     AppendDev el, po;
     int64_t* total_out;   // device: number of pairs of this call
+    int64_t* cnt;         // device: pairs of each cell (written by the count pass)
 };
 
 template <typename T>
@@ -142,7 +143,11 @@ __global__ void __launch_bounds__(kSwBlock) sw_total_kernel(SwArgs a) {
     int64_t v = 0;
     for (int q = 0; q < kSwPerThread; ++q) {
         const int64_t i = first + q * kSwBlock + threadIdx.x;
-        if (i < a.n) v += cell_pairs<T>(a, i);
+        if (i < a.n) {
+            const int64_t k = cell_pairs<T>(a, i);
+            a.cnt[i] = k;
+            v += k;
+        }
     }
     const int64_t t = block_sum(v, lds);
     if (threadIdx.x == 0) a.bsum[blockIdx.x] = t;
@@ -187,8 +192,9 @@ __device__ __forceinline__ void put(const AppendDev& o, int64_t slot, T w, T tau
 // range, so a block-wide exclusive scan of the thread totals orders the
 // pairs by cell.  base_e / base_p: the buffers' counts before this call
 // (count - total after the scan kernel).
-// The counts are computed with consecutive lanes on consecutive cells
-// (coalesced field loads) into LDS, then each thread takes its own cells'.
+// The count pass's per-cell counts are staged through LDS with consecutive
+// lanes on consecutive cells (coalesced), then each thread takes its own
+// cells'.
 template <typename T>
 __global__ void __launch_bounds__(kSwBlock) sw_write_kernel(SwArgs a) {
     __shared__ int64_t lds[kSwBlock / 64];
@@ -196,7 +202,7 @@ __global__ void __launch_bounds__(kSwBlock) sw_write_kernel(SwArgs a) {
     const int64_t bfirst = static_cast<int64_t>(blockIdx.x) * kSwCells;
     for (int q = 0; q < kSwPerThread; ++q) {
         const int64_t i = bfirst + q * kSwBlock + threadIdx.x;
-        cnt[q * kSwBlock + threadIdx.x] = i < a.n ? cell_pairs<T>(a, i) : 0;
+        cnt[q * kSwBlock + threadIdx.x] = i < a.n ? a.cnt[i] : 0;
     }
     __syncthreads();
     const int64_t first = bfirst + threadIdx.x * kSwPerThread;
@@ -291,7 +297,8 @@ extern "C" int32_t qed_schwinger_pairs(qed_context* ctx, const qed_cells* cells,
     if (cells->n == 0) return QED_OK;
     const int64_t nb = (cells->n + kSwCells - 1) / kSwCells;
     if (nb > INT32_MAX) { set_error("too many cells"); return QED_ERR_INVALID; }
-    if ((r = reserve_scratch(ctx, (nb + 1) * static_cast<int64_t>(sizeof(int64_t))))) return r;
+    // scratch: per-block totals, the call's total, then one count per cell
+    if ((r = reserve_scratch(ctx, (nb + 1 + cells->n) * static_cast<int64_t>(sizeof(int64_t))))) return r;
     SwArgs a = make_args(cells);
     a.scale = cell_volume * dt / weight;
     a.weight = weight;
@@ -299,6 +306,7 @@ extern "C" int32_t qed_schwinger_pairs(qed_context* ctx, const qed_cells* cells,
     a.step = step;
     a.bsum = static_cast<int64_t*>(ctx->d_scratch);
     a.total_out = a.bsum + nb;
+    a.cnt = a.total_out + 1;
     a.el = append_view(electrons);
     a.po = append_view(positrons);
     hipStream_t s = static_cast<hipStream_t>(stream);
