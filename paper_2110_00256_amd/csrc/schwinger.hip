@@ -72,9 +72,11 @@ __device__ double sw_rate(const SwArgs& a, int64_t i) {
     const double eps = sqrt(eps2), eta = sqrt(eta2);
     const double x = kPi * eta / eps;
     const double eta_coth = x < 1e-8 ? eps / kPi : eta / tanh(x);
-    // one exponential of the whole logarithm: exp(-pi/eps) alone would go
-    // subnormal (and lose its digits) long before the rate does
-    return exp(log(a.pref * eps * eta_coth) - kPi / eps);
+    const double pre = a.pref * eps * eta_coth, b = kPi / eps;
+    // exp(-b) is normal up to b = 708; beyond that it would go subnormal (and
+    // lose its digits) long before the rate does, so the rate is taken as one
+    // exponential of the whole logarithm there
+    return b < 700.0 ? pre * exp(-b) : exp(log(pre) - b);
 }
 
 __device__ int64_t sw_count(const SwArgs& a, double lambda, int64_t cell) {
