@@ -33,10 +33,13 @@ def _fields(n, seed, scale=0.15):
     rng = np.random.default_rng(seed)
     f = {k: rng.normal(size=n) * scale * ES for k in ("ex", "ey", "ez")}
     f.update({k: rng.normal(size=n) * scale * ES / C for k in ("bx", "by", "bz")})
-    # special cells: zero, pure B, crossed, pure E, parallel, weak
+    # special cells: zero, pure B, crossed, pure E, parallel, weak (rate
+    # underflows), pure E with pi/eps = 785 and 690 (a normal rate on either
+    # side of pi/eps = 700, where exp(-pi/eps) alone would start to lose digits)
     sp = [dict(ex=0, ey=0, ez=0, bx=0, by=0, bz=0), dict(ex=0, ey=0, ez=0, bx=0, by=0, bz=0.2 * ES / C),
           dict(ex=0, ey=0.3 * ES, ez=0, bx=0, by=0, bz=0.3 * ES / C), dict(ex=0.4 * ES, ey=0, ez=0, bx=0, by=0, bz=0),
-          dict(ex=0.2 * ES, ey=0, ez=0, bx=0.1 * ES / C, by=0, bz=0), dict(ex=1e-3 * ES, ey=0, ez=0, bx=0, by=0, bz=0)]
+          dict(ex=0.2 * ES, ey=0, ez=0, bx=0.1 * ES / C, by=0, bz=0), dict(ex=1e-3 * ES, ey=0, ez=0, bx=0, by=0, bz=0),
+          dict(ex=4e-3 * ES, ey=0, ez=0, bx=0, by=0, bz=0), dict(ex=4.55e-3 * ES, ey=0, ez=0, bx=0, by=0, bz=0)]
     for i, d in enumerate(sp[:n]):
         for k, v in d.items():
             f[k][i] = v
@@ -74,6 +77,8 @@ def test_rate_matches_oracle(ctx, dtype, n):
     assert np.all(g[~normal] < 1e-280)
     if n >= 6:
         assert g[0] == 0 and g[1] == 0 and g[2] == 0 and g[5] == 0 and g[3] > 0 and g[4] > 0
+    if n >= 8:
+        assert normal[6] and normal[7]   # both branches of the exponential checked
 
 
 def test_rate_empty(ctx):
