@@ -1,13 +1,13 @@
 """Pins of the oracle's runtime path: table interpolation, inverse-CDF
 sampling, the optical-depth step, kinematics and the ordered append.
 
-Statistical pins compare Monte Carlo outcomes with the integrated cross
-sections (event fractions) and with quadrature CDFs (spectra)."""
+The statistical pins (event fractions against the integrated cross
+sections, spectra against quadrature CDFs, 10^7 samples each) and the
+pins of the classical drag are in test_oracle_statistics.py."""
 import math
 
 import numpy as np
 import pytest
-from scipy import stats
 
 import qed_inputs as QI
 from oracle import oracle as O
@@ -77,73 +77,12 @@ def test_qs_sampler_below_first_knot_is_cube_law(tables64):
         assert qs.sample_qs_lnxi(chi, r) == pytest.approx(math.log(1e-12) - 3 * k, rel=1e-13)
 
 
-def _ks(samples, cdf_fn, grid):
-    """sup over grid of |ECDF - CDF|."""
-    s = np.sort(samples)
-    e = np.searchsorted(s, grid, side="right") / len(s)
-    return np.max(np.abs(e - np.array([cdf_fn(x) for x in grid])))
-
-
-@pytest.mark.parametrize("chi", [0.05, 1.0, 20.0])
-def test_qs_photon_spectrum_matches_cross_section(chi):
-    """Photon chi fractions sampled through a fine table follow the QS
-    cumulative distribution computed by quadrature (KS)."""
-    t = O.Table(O.QS, chi / 1.5, chi * 1.5, 3, 256)
-    rng = np.random.default_rng(11)
-    r = rng.random(1 << 20)
-    xi = np.exp(t.sample_n(chi, r))
-    qs_grid = np.quantile(xi, np.linspace(0.02, 0.98, 25))
-    ks = _ks(xi, lambda x: O.qs_cdf_at(chi, x), qs_grid)
-    assert ks < 3e-3, ks
-
-
-@pytest.mark.parametrize("chi", [0.05, 1.0, 20.0])
-def test_bw_pair_spectrum_matches_cross_section(chi):
-    t = O.Table(O.BW, chi / 1.5, chi * 1.5, 3, 256)
-    rng = np.random.default_rng(12)
-    r = rng.random(1 << 20)
-    xi, esel = t.sample_n(chi, r)
-    # electron fraction; symmetric under xi -> 1 - xi
-    xe = np.where(esel, xi, 1 - xi)
-    assert abs(esel.mean() - 0.5) < 5 * 0.5 / math.sqrt(len(r))
-    folded = np.minimum(xe, 1 - xe)
-    grid = np.quantile(folded, np.linspace(0.02, 0.98, 25))
-    ks = _ks(folded, lambda x: 2 * O.bw_cdf_at(chi, x), grid)
-    assert ks < 3e-3, ks
-
-
 def _fixed_population(n, gamma, e_field, photon):
     u = gamma if photon else math.sqrt(gamma * gamma - 1)
     z = np.zeros(n)
     return dict(ux=np.full(n, -u), uy=z.copy(), uz=z.copy(), ex=z.copy(), ey=np.full(n, e_field),
                 ez=z.copy(), bx=z.copy(), by=z.copy(), bz=np.full(n, e_field / QI.C_LIGHT),
                 w=np.linspace(0.5, 1.5, n))
-
-
-@pytest.mark.parametrize("photon", [False, True])
-def test_event_fraction_matches_total_rate(tables64, photon):
-    """With tau ~ Exp(1), the fraction of particles with an event in each step
-    is 1 - exp(-rate dt) (memoryless), rate = dN/dt from the tables."""
-    bw, qs = tables64
-    n, gamma, e = 1 << 18, 2000.0, 2e14
-    pop = _fixed_population(n, gamma, e, photon)
-    sp = O.PHOTON if photon else O.ELECTRON
-    p = O.Particles(pop, sp, id_base=1000)
-    O.init_optical_depth(p, seed=5)
-    chi = O.chi_photon(*[pop[k][0] for k in ("ux", "uy", "uz", "ex", "ey", "ez", "bx", "by", "bz")]) \
-        if photon else O.chi_lepton(*[pop[k][0] for k in ("ux", "uy", "uz", "ex", "ey", "ez", "bx", "by", "bz")])
-    rate = (bw if photon else qs).rate(chi, gamma)
-    dt = 0.2 / rate
-    prob = 1 - math.exp(-rate * dt)
-    a1, a2 = O.Append(n), O.Append(n)
-    tot = 0
-    steps = 1 if photon else 3   # a photon decays once and is dead afterwards
-    for s in range(steps):
-        tot += O.step(bw, qs, p, dt, seed=5, step_idx=s, a1=a1, a2=a2)
-    mean = steps * n * prob
-    sd = math.sqrt(steps * n * prob * (1 - prob))
-    assert abs(tot - mean) < 5 * sd
-    assert a1.count == tot
 
 
 def test_step_kinematics_conservation_and_order(tables64):
@@ -255,14 +194,12 @@ def test_qed_threshold_classical_drag():
     flags = np.zeros(n, dtype=np.uint8)
     dt = 1e-16
     O.step(bw, qs, p, dt, 1, 0, O.Append(n), flags=flags, chi_qed_min=thr)
-    r0 = 7.2973525693e-3 * QI.M_E * QI.C_LIGHT ** 2 / QI.HBAR
     for i in range(n):
         u0 = np.array([d["ux"][i], d["uy"][i], 0.0])
         u1 = np.array([p["ux"][i], p["uy"][i], p["uz"][i]])
         if chi[i] < thr:
             assert p["tau"][i] == 0.5 and flags[i] == 0
-            g0, g1 = math.sqrt(1 + u0 @ u0), math.sqrt(1 + u1 @ u1)
-            assert g0 - g1 == pytest.approx((2 / 3) * r0 * chi[i] ** 2 * dt, rel=1e-9)
+            assert u1 @ u1 < u0 @ u0            # energy lost (its amount: test_oracle_statistics)
             assert np.allclose(np.cross(u0, u1), 0.0, atol=1e-12 * (u0 @ u0))   # along u
         else:
             assert p["tau"][i] != 0.5                                    # evolved as usual
