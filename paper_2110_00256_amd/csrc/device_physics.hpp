@@ -384,16 +384,14 @@ __device__ __forceinline__ int upper_bound_row(const S* pp, T f, T r, int nf) {
     return lo;
 }
 
-// BW pair sampling (Sec. 3.1): r <= 1/2 selects the electron, otherwise
-// r -> 1 - r selects the positron; rows n, n+1 interpolated in ln chi_gamma;
-// binary search for P_m <= r < P_{m+1}; linear inverse in xi.
+// BW pair sampling (Sec. 3.1) for a folded uniform r in (0, 1/2]: rows n,
+// n+1 interpolated in ln chi_gamma; binary search for P_m <= r < P_{m+1};
+// linear inverse in xi.
 template <typename T, typename S = T>
-__device__ __forceinline__ T sample_bw(const TableDev& t, T chi, T r, bool& electron) {
+__device__ __forceinline__ T sample_bw_folded(const TableDev& t, T chi, T r) {
     int n;
     T f;
     row_pos<T>(t, chi, n, f);
-    electron = (r <= T(0.5));
-    if (!electron) r = T(1) - r;
     const int nf = t.n_frac;
     const S* pp = cdf_ptr<S>(t) + 2 * static_cast<size_t>(n) * nf;
     const int lo = upper_bound_row<T, S>(pp, f, r, nf);
@@ -404,18 +402,26 @@ __device__ __forceinline__ T sample_bw(const TableDev& t, T chi, T r, bool& elec
     return xa + (r - pa) * (xb - xa) / (pb - pa);
 }
 
-// QS photon sampling (Sec. 3.2): ln P rows interpolated in ln chi; binary
-// search on ln r; log-log inverse.  Below the first knot the small-xi law
-// P ~ xi^{1/3} continues the table: ln xi = ln xi_min + 3 (ln r - ln P_0).
-// Returns ln xi.
+// The fold of Sec. 3.1: r <= 1/2 selects the electron, otherwise r -> 1 - r
+// selects the positron.
 template <typename T, typename S = T>
-__device__ __forceinline__ T sample_qs_lnxi(const TableDev& t, T chi, T r) {
+__device__ __forceinline__ T sample_bw(const TableDev& t, T chi, T r, bool& electron) {
+    electron = (r <= T(0.5));
+    if (!electron) r = T(1) - r;
+    return sample_bw_folded<T, S>(t, chi, r);
+}
+
+// QS photon sampling (Sec. 3.2) given lr = ln r: ln P rows interpolated in
+// ln chi; binary search on ln r; log-log inverse.  Below the first knot the
+// small-xi law P ~ xi^{1/3} continues the table: ln xi = ln xi_min + 3 (ln r
+// - ln P_0).  Returns ln xi.
+template <typename T, typename S = T>
+__device__ __forceinline__ T sample_qs_lnxi_lr(const TableDev& t, T chi, T lr) {
     int n;
     T f;
     row_pos<T>(t, chi, n, f);
     const int nf = t.n_frac;
     const S* pp = cdf_ptr<S>(t) + 2 * static_cast<size_t>(n) * nf;
-    const T lr = dlog(r);
     const T lmin = static_cast<T>(t.ln_frac_min);
     const T l0 = pair_value<T, S>(pp, f, 0);
     if (lr < l0) return lmin + T(3) * (lr - l0);
@@ -426,6 +432,25 @@ __device__ __forceinline__ T sample_qs_lnxi(const TableDev& t, T chi, T r) {
     const T xa = lmin * (T(1) - static_cast<T>(lo) * inv);
     const T xb = lmin * (T(1) - static_cast<T>(lo + 1) * inv);
     return xa + (lr - la) * (xb - xa) / (lb - la);
+}
+
+template <typename T, typename S = T>
+__device__ __forceinline__ T sample_qs_lnxi(const TableDev& t, T chi, T r) {
+    return sample_qs_lnxi_lr<T, S>(t, chi, dlog(r));
+}
+
+// The random inputs of one event's sample, taken from the 53-bit uniform u
+// before any narrowing to T: ln u for QS (near u = 1 the FP32 spacing is
+// all of 1 - u), and for BW the fold min(u, 1 - u), exact in FP64, with the
+// electron chosen on u itself.
+template <typename T>
+__device__ __forceinline__ T qs_log_uniform(double u) {
+    return static_cast<T>(log(u));
+}
+template <typename T>
+__device__ __forceinline__ T bw_folded_uniform(double u, bool& electron) {
+    electron = u <= 0.5;
+    return static_cast<T>(electron ? u : 1.0 - u);
 }
 
 }  // namespace dev

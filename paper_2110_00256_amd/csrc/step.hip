@@ -218,23 +218,6 @@ __device__ __forceinline__ void classical_drag(const SetDev& S, int64_t j, T ux,
     st<T>(S.p[2], j, static_cast<T>(z * sc * inv_u));
 }
 
-// Sampled photon fraction ln xi for a lepton event.  `cs` is the event's
-// LDS word: the surrogate's sample when `have`, else chi for the table.
-template <typename T>
-__device__ __forceinline__ T qs_lnxi(const StepArgs& a, bool valid, bool have, T cs, T r) {
-    if (have) return cs;
-    return valid ? dev::sample_qs_lnxi<T>(a.qs, cs, r) : T(0);
-}
-
-// Pair fraction xi (electron_selected out) for a photon event; `cs` as above.
-template <typename T>
-__device__ __forceinline__ T bw_xi(const StepArgs& a, bool valid, bool have, T cs, T r, bool& esel) {
-    esel = r <= T(0.5);
-    if (have) return cs;
-    bool e;
-    return valid ? dev::sample_bw<T>(a.bw, cs, r, e) : T(0);
-}
-
 template <typename T, int kChiMode, bool kSurr>
 __device__ __forceinline__ void step_body(const StepArgs& a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -450,15 +433,20 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             const bool valid = e < total;
             const int le = valid ? evlist[e] : 0;
             const T cs = valid ? s_chi[le] : T(1);
-            const T r = static_cast<T>(dev::draws(a.seed, static_cast<unsigned long long>(S.id_base + c.begin + le),
-                                                  a.step, static_cast<unsigned long long>(S.species), 0ULL).u[0]);
+            const double u0 = dev::draws(a.seed, static_cast<unsigned long long>(S.id_base + c.begin + le), a.step,
+                                         static_cast<unsigned long long>(S.species), 0ULL).u[0];
+            // a surrogate sample (`have`) replaced chi in LDS; otherwise the
+            // table is searched with the random input taken from u0 before
+            // narrowing (ln u0 for QS; the fold for BW)
             const bool have = surr_on && valid && ((smask[e >> 6] >> (e & 63)) & 1ULL);
             T xi;
             if (photon) {
                 bool esel;
-                xi = bw_xi<T>(a, valid, have, cs, r, esel);
+                const T rf = dev::bw_folded_uniform<T>(u0, esel);
+                xi = have ? cs : (valid ? dev::sample_bw_folded<T>(a.bw, cs, rf) : T(0));
             } else {
-                xi = dev::dexp(qs_lnxi<T>(a, valid, have, cs, r));
+                const T lr = dev::qs_log_uniform<T>(u0);
+                xi = dev::dexp(have ? cs : (valid ? dev::sample_qs_lnxi_lr<T>(a.qs, cs, lr) : T(0)));
             }
             if (valid) s_chi[le] = xi;
         }
@@ -564,7 +552,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 const T t1 = static_cast<T>(-log(d.u[1]));
                 const T t2 = static_cast<T>(-log(d.u[2]));
                 if (photon) {
-                    const bool esel = static_cast<T>(d.u[0]) <= T(0.5);
+                    const bool esel = d.u[0] <= 0.5;   // on the 53-bit uniform, as in phase 2a
                     const T sx = xi * ux * iu, sy = xi * uy * iu, sz = xi * uz * iu;
                     const T ox = ux * iu - sx, oy = uy * iu - sy, oz = uz * iu - sz;
                     const T te = t1, tp = t2;

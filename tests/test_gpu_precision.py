@@ -179,8 +179,9 @@ def test_table_precision(ctx, cone, tabs):
         res[f"{name}/live_rate_fraction"] = float(live.mean())
     report("tables_cone_256", res)
     # FP32 storage + FP32 arithmetic: ln-rate interpolation error of a few
-    # FP32 ulps of |ln rate| (<= ~40 here), through exp
-    assert res["qs/rate/fp32"]["max"] < 2e-4 and res["bw/rate/fp32"]["max"] < 2e-4
+    # FP32 ulps of |ln rate| (<= ~40 here), through exp; within the rate-error
+    # gate of 1e-4
+    assert res["qs/rate/fp32"]["max"] < 1e-4 and res["bw/rate/fp32"]["max"] < 1e-4
     assert res["qs/rate/fp32"]["median"] < 1e-6 and res["bw/rate/fp32"]["median"] < 1e-6
     assert res["bw/xi_abs/fp32"]["median"] < 1e-6 and res["qs/lnxi_abs/fp32"]["median"] < 1e-5
 
@@ -253,14 +254,12 @@ def test_step_precision(ctx, cone, tabs, chi_mode):
     mname = "fp64" if chi_mode == Q.CHI_FP64 else "comp32"
     report(f"step_cone_fp32_chi_{mname}", res)
     assert far_flips == 0, "event flip away from tau = 0"
-    # The FP32 path rounds the uniform of the sampling draw to FP32: near
-    # r -> 1 (the hardest photons, where ln P is flat) the FP32 spacing 6e-8
-    # below 1 moves xi by up to ~1e-3 of |u|, for a handful of events in
-    # 2^25; everything else is at the 1e-5 bar.
+    # The sampling's random inputs come from the 53-bit uniform before
+    # narrowing (ln r for QS, the fold and the electron choice for BW), so
+    # every momentum and optical depth is within the FP32 bar of 1e-5.
     for k, v in res.items():
         if k.endswith("_missing"):
             assert v == 0, k
         if k.endswith("_rel"):
-            assert v.get("max", 0.0) < 1e-2, k
-            assert v.get("p99.99", 0.0) < 1e-5, k
-            assert v.get("median", 0.0) < 1e-6, k
+            assert v.get("max", 0.0) < 1e-5, (k, v)
+            assert v.get("median", 0.0) < 1e-6, (k, v)
