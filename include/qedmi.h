@@ -260,7 +260,13 @@ int32_t qed_table_sample(const qed_table* t, int32_t dtype, const void* chi, con
  * tiles (host, may be NULL): n_tiles triples (set, begin, end) splitting
  * set `set` of `sets` into [begin, end) ranges; products follow tile order.
  * NULL means one tile per set, in set order.  Tiles of one set must be
- * disjoint; tiles may not cover ions. */
+ * disjoint (an overlap is refused with QED_ERR_INVALID before anything is
+ * launched); tiles over ions are allowed and skipped.  The tile list is
+ * copied during the call (through the context's pinned staging), so the
+ * caller may reuse it at once; the chunk table is built on the device and
+ * rebuilt only when the tile list or the set sizes change.  The call does
+ * not block the host, except when the context's scratch must grow (a larger
+ * population or more tiles than any earlier call). */
 typedef struct qed_surrogate qed_surrogate;
 
 typedef struct {
@@ -299,6 +305,11 @@ enum {
     QED_STAT_PHOTONS_KEPT = 3,   /* photons appended (before capacity)     */
     QED_STAT_SURR_BATCHES = 4,   /* event batches sampled by a surrogate   */
     QED_STAT_SURR_FALLBACK = 5,  /* event batches that fell back to tables */
+    QED_STAT_NONFINITE = 6,      /* particles whose chi is not finite or whose
+                                    updated optical depth is NaN or -inf (bad
+                                    momenta or fields); they are stepped as
+                                    the arithmetic gives, only counted here.
+                                    +inf (a decayed photon) is not counted */
     QED_STAT_SCAN_TIMEOUT = 7,   /* look-back waits abandoned (must stay 0) */
     QED_STATS_LEN = 8
 };

@@ -21,7 +21,7 @@ BW, QS = 0, 1
 ELECTRON, POSITRON, PHOTON, ION = 0, 1, 2, 3
 CHI_FP64, CHI_COMP32, CHI_FP32 = 0, 1, 2
 STAT_UPDATES, STAT_QS_EVENTS, STAT_BW_EVENTS, STAT_PHOTONS_KEPT = 0, 1, 2, 3
-STAT_SURR_BATCHES, STAT_SURR_FALLBACK, STAT_SCAN_TIMEOUT, STATS_LEN = 4, 5, 7, 8
+STAT_SURR_BATCHES, STAT_SURR_FALLBACK, STAT_NONFINITE, STAT_SCAN_TIMEOUT, STATS_LEN = 4, 5, 6, 7, 8
 SURR_NPARAM = 64 * 2 + 64 + 64 * 64 + 64 + 64 + 1
 
 # Every symbol the header declares (checked by the CPU test suite).

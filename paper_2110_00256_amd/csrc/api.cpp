@@ -1,6 +1,7 @@
 // C-ABI layer: argument validation, contexts, chunk tables, launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -91,34 +92,93 @@ AppendDev to_append(const qed_append* a) {
     return d;
 }
 
-// Ensure the context's scratch can hold n chunks.
-int32_t reserve(qed_context* ctx, int64_t n_chunks) {
-    if (n_chunks <= ctx->status_cap && n_chunks <= ctx->chunks_cap) return QED_OK;
-    const int64_t cap = std::max<int64_t>(n_chunks, 2 * ctx->status_cap);
-    unsigned long long* st = nullptr;
-    ChunkDesc* ch = nullptr;
-    if (hipMalloc(&st, sizeof(unsigned long long) * cap) != hipSuccess ||
-        hipMalloc(&ch, sizeof(ChunkDesc) * cap) != hipSuccess) {
-        hipFree(st);
-        set_error("device allocation of scan scratch failed");
-        return QED_ERR_ALLOC;
+// Grow the context's device scratch to hold n_chunks chunks (look-back
+// status words, chunk table) and n_tiles tiles (tile list, builder order and
+// start arrays).  Growth waits for queued work before freeing the old
+// buffers; a steady workload never grows.
+int32_t reserve(qed_context* ctx, int64_t n_chunks, int64_t n_tiles) {
+    n_chunks = std::max<int64_t>(n_chunks, 1);
+    n_tiles = std::max<int64_t>(n_tiles, 1);
+    if (n_chunks > ctx->status_cap || n_chunks > ctx->chunks_cap) {
+        const int64_t cap = std::max<int64_t>(n_chunks, 2 * ctx->status_cap);
+        unsigned long long* st = nullptr;
+        ChunkDesc* ch = nullptr;
+        if (hipMalloc(&st, sizeof(unsigned long long) * cap) != hipSuccess ||
+            hipMalloc(&ch, sizeof(ChunkDesc) * cap) != hipSuccess) {
+            hipFree(st);
+            set_error("device allocation of scan scratch failed");
+            return QED_ERR_ALLOC;
+        }
+        if (hipMemset(st, 0, sizeof(unsigned long long) * cap) != hipSuccess) {
+            hipFree(st);
+            hipFree(ch);
+            set_error("memset of scan scratch failed");
+            return QED_ERR_HIP;
+        }
+        // old scratch may still be in use by queued work: wait before freeing
+        hipDeviceSynchronize();
+        hipFree(ctx->d_status);
+        hipFree(ctx->d_chunks);
+        ctx->d_status = st;
+        ctx->d_chunks = ch;
+        ctx->status_cap = cap;
+        ctx->chunks_cap = cap;
+        ctx->layout_valid = false;
     }
-    if (hipMemset(st, 0, sizeof(unsigned long long) * cap) != hipSuccess) {
-        hipFree(st);
-        hipFree(ch);
-        set_error("memset of scan scratch failed");
-        return QED_ERR_HIP;
+    if (n_tiles > ctx->tiles_cap) {
+        const int64_t cap = std::max<int64_t>(n_tiles, 2 * ctx->tiles_cap);
+        int64_t* t = nullptr;
+        int32_t* q = nullptr;
+        if (hipMalloc(&t, sizeof(int64_t) * 3 * cap) != hipSuccess ||
+            hipMalloc(&q, sizeof(int32_t) * 2 * cap) != hipSuccess) {
+            hipFree(t);
+            set_error("device allocation of the tile list failed");
+            return QED_ERR_ALLOC;
+        }
+        hipDeviceSynchronize();
+        hipFree(ctx->d_tiles);
+        hipFree(ctx->d_part);
+        ctx->d_tiles = t;
+        ctx->d_part = q;
+        ctx->tiles_cap = cap;
+        ctx->layout_valid = false;
     }
-    // old scratch may still be in use by queued work: wait before freeing
-    hipDeviceSynchronize();
-    hipFree(ctx->d_status);
-    hipFree(ctx->d_chunks);
-    ctx->d_status = st;
-    ctx->d_chunks = ch;
-    ctx->status_cap = cap;
-    ctx->chunks_cap = cap;
-    ctx->h_chunks_cached.clear();
     return QED_OK;
+}
+
+// Copy the caller's tile list to the device through pinned staging, with no
+// host synchronisation: the copy reads buffer `stage_next`, which is reused
+// only after the copy issued from it two calls earlier has completed.
+int32_t stage_tiles(qed_context* ctx, const int64_t* tiles, int32_t n_tiles, hipStream_t s) {
+    const int64_t words = 3 * static_cast<int64_t>(n_tiles);
+    if (words > ctx->stage_cap) {
+        const int64_t cap = std::max<int64_t>(words, 2 * ctx->stage_cap);
+        for (int i = 0; i < 2; ++i) {
+            if (ctx->stage_ev[i]) hipEventSynchronize(ctx->stage_ev[i]);
+            hipHostFree(ctx->h_stage[i]);
+            ctx->h_stage[i] = nullptr;
+        }
+        ctx->stage_cap = 0;
+        for (int i = 0; i < 2; ++i) {
+            if (hipHostMalloc(reinterpret_cast<void**>(&ctx->h_stage[i]), sizeof(int64_t) * cap) != hipSuccess) {
+                set_error("pinned host allocation of the tile staging failed");
+                return QED_ERR_ALLOC;
+            }
+            if (!ctx->stage_ev[i] && hipEventCreateWithFlags(&ctx->stage_ev[i], hipEventDisableTiming) != hipSuccess) {
+                set_error("event creation failed");
+                return QED_ERR_HIP;
+            }
+        }
+        ctx->stage_cap = cap;
+    }
+    const int i = ctx->stage_next;
+    ctx->stage_next ^= 1;
+    hipError_t e = hipEventSynchronize(ctx->stage_ev[i]);   // the copy of two calls ago
+    if (e != hipSuccess) return hip_fail(e, "tile staging wait");
+    std::memcpy(ctx->h_stage[i], tiles, sizeof(int64_t) * words);
+    e = hipMemcpyAsync(ctx->d_tiles, ctx->h_stage[i], sizeof(int64_t) * words, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(ctx->stage_ev[i], s);
+    return e == hipSuccess ? QED_OK : hip_fail(e, "tile list upload");
 }
 
 }  // namespace
@@ -146,83 +206,16 @@ int32_t reserve_scratch(qed_context* ctx, int64_t bytes) {
 
 namespace {
 
-// Build chunks ordered by (stream, tile order) and upload them if they
-// differ from the cached table.
-int32_t build_chunks(qed_context* ctx, const std::vector<SetDev>& sets, const int64_t* tiles, int n_tiles,
-                     hipStream_t s, int32_t* n_chunks_out) {
-    std::vector<int64_t> tl;
-    if (tiles) {
-        tl.assign(tiles, tiles + 3 * static_cast<size_t>(n_tiles));
-    } else {
-        for (size_t i = 0; i < sets.size(); ++i) {
-            tl.push_back(static_cast<int64_t>(i));
-            tl.push_back(0);
-            tl.push_back(sets[i].n);
-        }
-        n_tiles = static_cast<int>(sets.size());
-    }
-    std::vector<ChunkDesc> ch;
-    int64_t per_stream[2] = {0, 0};
-    for (int stream = 0; stream < 2; ++stream) {
-        const int first = static_cast<int>(ch.size());
-        for (int t = 0; t < n_tiles; ++t) {
-            const int64_t set = tl[3 * t], b = tl[3 * t + 1], e = tl[3 * t + 2];
-            if (set < 0 || set >= static_cast<int64_t>(sets.size()) || b < 0 || e < b || e > sets[set].n) {
-                set_error("tile out of range of its set");
-                return QED_ERR_INVALID;
-            }
-            if (sets[set].stream != stream) continue;
-            per_stream[stream] += e - b;
-            for (int64_t x = b; x < e; x += kChunk) {
-                ChunkDesc c{};
-                c.begin = x;
-                c.set = static_cast<int32_t>(set);
-                c.len = static_cast<int32_t>(std::min<int64_t>(kChunk, e - x));
-                c.stream = stream;
-                c.stream_first = first;
-                ch.push_back(c);
-            }
-        }
-        for (size_t i = first; i < ch.size(); ++i) ch[i].stream_last = static_cast<int32_t>(ch.size() - 1);
-    }
-    if (per_stream[0] >= (1LL << kStatusBits) || per_stream[1] >= (1LL << kStatusBits)) {
-        set_error("more than 2^30 - 1 particles in one product stream");
-        return QED_ERR_INVALID;
-    }
-    if (ch.size() > static_cast<size_t>(INT_MAX / 2)) { set_error("too many chunks"); return QED_ERR_INVALID; }
-    const int32_t r = reserve(ctx, std::max<int64_t>(1, static_cast<int64_t>(ch.size())));
-    if (r != QED_OK) return r;
-    const bool same = ch.size() == ctx->h_chunks_cached.size() &&
-                      (ch.empty() || std::memcmp(ch.data(), ctx->h_chunks_cached.data(),
-                                                 ch.size() * sizeof(ChunkDesc)) == 0);
-    if (!same && !ch.empty()) {
-        ctx->h_chunks_cached = ch;   // kept alive: the async copy reads it
-        const hipError_t e = hipMemcpyAsync(ctx->d_chunks, ctx->h_chunks_cached.data(), ch.size() * sizeof(ChunkDesc),
-                                            hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) return hip_fail(e, "chunk table upload");
-        hipStreamSynchronize(s);
-    }
-    *n_chunks_out = static_cast<int32_t>(ch.size());
-    return QED_OK;
-}
-
-int32_t launch_chunks(qed_context* ctx, StepArgs& a, int dtype, hipStream_t s) {
-    if (a.n_chunks == 0) return QED_OK;
-    int dev = 0;
-    hipGetDevice(&dev);
-    if (dev != ctx->device) { set_error("context belongs to another device"); return QED_ERR_INVALID; }
-    const int grid = std::max(1, std::min(a.n_chunks, step_grid_size(a, dtype, ctx->device)));
-    ctx->epoch = ctx->epoch + 1 == 0 ? 1 : ctx->epoch + 1;
-    a.status = ctx->d_status;
-    a.ticket = ctx->d_ticket;
-    a.ticket_base = ctx->ticket_issued;
-    a.epoch = ctx->epoch;
-    a.chunks = ctx->d_chunks;
-    const hipError_t e = launch_step(a, dtype, grid, s);
-    if (e != hipSuccess) return hip_fail(e, "step launch");
-    // every block takes exactly one failing ticket before it exits
-    ctx->ticket_issued += static_cast<unsigned long long>(a.n_chunks) + static_cast<unsigned long long>(grid);
-    return QED_OK;
+// Persistent grid of the step kernel variant this launch uses, queried
+// once per variant and LDS size.
+int cached_grid(qed_context* ctx, const StepArgs& a, int dtype) {
+    const int surr = (a.use_bw_surr || a.use_qs_surr) ? 1 : 0;
+    const size_t lds = step_lds_bytes_for(a, dtype);
+    for (const auto& g : ctx->grids)
+        if (g.dtype == dtype && g.surr == surr && g.chi_mode == a.chi_mode && g.lds == lds) return g.grid;
+    const int grid = step_grid_size(a, dtype, ctx->device);
+    ctx->grids.push_back({dtype, surr, a.chi_mode, lds, grid});
+    return grid;
 }
 
 }  // namespace
@@ -305,7 +298,13 @@ extern "C" void qed_context_destroy(qed_context* c) {
     hipFree(c->d_ticket);
     hipFree(c->d_status);
     hipFree(c->d_chunks);
+    hipFree(c->d_tiles);
+    hipFree(c->d_part);
     hipFree(c->d_scratch);
+    for (int i = 0; i < 2; ++i) {
+        hipHostFree(c->h_stage[i]);
+        if (c->stage_ev[i]) hipEventDestroy(c->stage_ev[i]);
+    }
     hipSetDevice(cur);
     delete c;
 }
@@ -378,8 +377,9 @@ extern "C" int32_t qed_evolve_optical_depth(qed_context* ctx, const qed_table* r
     return e == hipSuccess ? QED_OK : hip_fail(e, "evolve launch");
 }
 
-static int32_t run_chunks(qed_context* ctx, const qed_step_desc* d, bool generate_only, hipStream_t s) {
-    if (!ctx) { set_error("context is null"); return QED_ERR_INVALID; }
+namespace qedmi {
+
+int32_t prepare_sets(const qed_step_desc* d, bool generate_only, StepArgs& a, int& dtype) {
     if (!d) { set_error("desc is null"); return QED_ERR_INVALID; }
     if (d->n_sets <= 0 || d->n_sets > kMaxSets || !d->sets) { set_error("need 1..8 particle sets"); return QED_ERR_INVALID; }
     if (d->n_tiles < 0 || (d->n_tiles > 0 && !d->tiles)) { set_error("bad tiles"); return QED_ERR_INVALID; }
@@ -387,9 +387,8 @@ static int32_t run_chunks(qed_context* ctx, const qed_step_desc* d, bool generat
     if (!(d->photon_min_energy >= 0.0)) { set_error("photon_min_energy must be >= 0"); return QED_ERR_INVALID; }
     if (!(d->chi_qed_min >= 0.0)) { set_error("chi_qed_min must be >= 0"); return QED_ERR_INVALID; }
     if (d->chi_mode < QED_CHI_FP64 || d->chi_mode > QED_CHI_FP32) { set_error("bad chi_mode"); return QED_ERR_INVALID; }
-    const int dtype = d->sets[0].dtype;
-    bool any_lepton = false, any_photon = false;
-    std::vector<SetDev> sets;
+    a = StepArgs{};
+    dtype = d->sets[0].dtype;
     for (int i = 0; i < d->n_sets; ++i) {
         const qed_particles& p = d->sets[i];
         int32_t r = check_particles(&p, true);
@@ -397,11 +396,19 @@ static int32_t run_chunks(qed_context* ctx, const qed_step_desc* d, bool generat
         if (p.dtype != dtype) { set_error("all sets must share one dtype"); return QED_ERR_INVALID; }
         uint8_t* fl = d->flags ? d->flags[i] : nullptr;
         if (generate_only && !fl && p.n > 0 && p.species != QED_ION) { set_error("flags required"); return QED_ERR_INVALID; }
-        if (p.n > 0 && is_lepton(p.species)) any_lepton = true;
-        if (p.n > 0 && p.species == QED_PHOTON) any_photon = true;
-        sets.push_back(to_set(p, fl));
+        a.sets[i] = to_set(p, fl);
     }
-    StepArgs a{};
+    a.n_sets = d->n_sets;
+    a.generate_only = generate_only ? 1 : 0;
+    return QED_OK;
+}
+
+int32_t prepare_tables(const Units& units, const qed_step_desc* d, StepArgs& a, int dtype) {
+    bool any_lepton = false, any_photon = false;
+    for (int i = 0; i < a.n_sets; ++i) {
+        if (a.sets[i].n > 0 && a.sets[i].stream == 0) any_lepton = true;
+        if (a.sets[i].n > 0 && a.sets[i].stream == 1) any_photon = true;
+    }
     if (any_photon) {
         int32_t r = check_table(d->bw, QED_PROC_BW, "BW");
         if (!r) r = check_append(d->electrons, dtype, "electrons");
@@ -415,22 +422,15 @@ static int32_t run_chunks(qed_context* ctx, const qed_step_desc* d, bool generat
         if (r) return r;
         a.qs = d->qs->view();
     }
-    int32_t n_chunks = 0;
-    int32_t r = build_chunks(ctx, sets, d->n_tiles > 0 ? d->tiles : nullptr, d->n_tiles, s, &n_chunks);
-    if (r) return r;
-    for (size_t i = 0; i < sets.size(); ++i) a.sets[i] = sets[i];
-    a.n_sets = static_cast<int32_t>(sets.size());
-    a.n_chunks = n_chunks;
-    a.generate_only = generate_only ? 1 : 0;
     a.ph = to_append(any_lepton ? d->photons : nullptr);
     a.el = to_append(any_photon ? d->electrons : nullptr);
     a.po = to_append(any_photon ? d->positrons : nullptr);
     a.stats = d->stats;
-    a.dt = d->dt * ctx->units.t;
-    a.units = ctx->units;
+    a.dt = d->dt * units.t;
+    a.units = units;
     a.seed = d->seed;
     a.step = d->step;
-    a.photon_min_energy = d->photon_min_energy * ctx->units.energy;
+    a.photon_min_energy = d->photon_min_energy * units.energy;
     a.chi_qed_min = d->chi_qed_min;
     a.drag = (2.0 / 3.0) * kRateR0 * a.dt;
     a.chi_mode = dtype == QED_FP64 ? QED_CHI_FP64 : d->chi_mode;
@@ -438,9 +438,148 @@ static int32_t run_chunks(qed_context* ctx, const qed_step_desc* d, bool generat
         set_error("surrogate sampling runs on the FP32 path only");
         return QED_ERR_INVALID;
     }
-    r = surrogate_bind(a, d->bw_surrogate, d->qs_surrogate);
+    return surrogate_bind(a, d->bw_surrogate, d->qs_surrogate);
+}
+
+int32_t plan_chunks(const StepArgs& a, const int64_t* tiles, int32_t n_tiles, int32_t* idx, ChunkPlan& plan) {
+    plan = ChunkPlan{};
+    const int nt = tiles ? n_tiles : a.n_sets;
+    int64_t per_stream[2] = {0, 0};
+    int64_t chunks[2] = {0, 0};
+    int32_t parts[2] = {0, 0};
+    int64_t last_end[kMaxSets];
+    for (int i = 0; i < kMaxSets; ++i) last_end[i] = 0;
+    bool ordered = true;   // every set's (non-empty) tiles come in increasing, disjoint order
+    for (int t = 0; t < nt; ++t) {
+        const int64_t set = tiles ? tiles[3 * t] : t;
+        const int64_t b = tiles ? tiles[3 * t + 1] : 0;
+        const int64_t e = tiles ? tiles[3 * t + 2] : a.sets[t].n;
+        if (set < 0 || set >= a.n_sets || b < 0 || e < b || e > a.sets[set].n) {
+            set_error("tile out of range of its set");
+            return QED_ERR_INVALID;
+        }
+        if (e == b) continue;
+        if (b < last_end[set]) ordered = false;
+        last_end[set] = std::max(last_end[set], e);
+        const int stream = a.sets[set].stream;
+        if (stream < 0) continue;   // ions: passed through, never read
+        per_stream[stream] += e - b;
+        chunks[stream] += (e - b + kChunk - 1) / kChunk;
+        parts[stream] += 1;
+    }
+    if (!ordered) {
+        // sort the non-empty tiles by (set, begin) and look for an overlap
+        int m = 0;
+        for (int t = 0; t < nt; ++t)
+            if (tiles[3 * t + 2] > tiles[3 * t + 1]) idx[m++] = t;
+        std::sort(idx, idx + m, [tiles](int32_t x, int32_t y) {
+            return tiles[3 * x] != tiles[3 * y] ? tiles[3 * x] < tiles[3 * y] : tiles[3 * x + 1] < tiles[3 * y + 1];
+        });
+        for (int i = 1; i < m; ++i) {
+            const int32_t p = idx[i - 1], q = idx[i];
+            if (tiles[3 * p] == tiles[3 * q] && tiles[3 * q + 1] < tiles[3 * p + 2]) {
+                set_error("tiles of one set overlap");
+                return QED_ERR_INVALID;
+            }
+        }
+    }
+    if (per_stream[0] >= (1LL << kStatusBits) || per_stream[1] >= (1LL << kStatusBits)) {
+        set_error("more than 2^30 - 1 particles in one product stream");
+        return QED_ERR_INVALID;
+    }
+    if (chunks[0] + chunks[1] > INT_MAX / 2) { set_error("too many chunks"); return QED_ERR_INVALID; }
+    plan.n_tiles = nt;
+    plan.n_part0 = parts[0];
+    plan.n_part = parts[0] + parts[1];
+    plan.n_chunks0 = static_cast<int32_t>(chunks[0]);
+    plan.n_chunks = static_cast<int32_t>(chunks[0] + chunks[1]);
+    return QED_OK;
+}
+
+ChunkBuildArgs chunk_build_args(const StepArgs& a, const ChunkPlan& plan) {
+    ChunkBuildArgs b{};
+    b.n_tiles = plan.n_tiles;
+    b.n_part0 = plan.n_part0;
+    b.n_part = plan.n_part;
+    b.n_chunks0 = plan.n_chunks0;
+    b.n_chunks = plan.n_chunks;
+    for (int i = 0; i < a.n_sets; ++i) {
+        b.set_stream[i] = a.sets[i].stream;
+        b.set_n[i] = a.sets[i].n;
+    }
+    return b;
+}
+
+}  // namespace qedmi
+
+static int32_t run_chunks(qed_context* ctx, const qed_step_desc* d, bool generate_only, hipStream_t s) {
+    // the descriptor and its tiles are checked first (no HIP call), then
+    // the context, the tables and the buffers
+    StepArgs a;
+    int dtype = 0;
+    int32_t r = prepare_sets(d, generate_only, a, dtype);
     if (r) return r;
-    return launch_chunks(ctx, a, dtype, s);
+    const int64_t* tiles = d->n_tiles > 0 ? d->tiles : nullptr;
+    std::vector<int32_t> local_idx;
+    std::vector<int32_t>& idx = ctx ? ctx->tile_idx : local_idx;
+    if (tiles && idx.size() < static_cast<size_t>(d->n_tiles)) idx.resize(d->n_tiles);
+    ChunkPlan plan;
+    r = plan_chunks(a, tiles, d->n_tiles, idx.data(), plan);
+    if (r) return r;
+    if (!ctx) { set_error("context is null"); return QED_ERR_INVALID; }
+    int dev = 0;
+    hipGetDevice(&dev);
+    if (dev != ctx->device) { set_error("context belongs to another device"); return QED_ERR_INVALID; }
+    r = prepare_tables(ctx->units, d, a, dtype);
+    if (r) return r;
+    if (plan.n_chunks == 0) return QED_OK;
+    r = reserve(ctx, plan.n_chunks, plan.n_tiles);
+    if (r) return r;
+    // the chunk table on the device is rebuilt only when the layout (set
+    // sizes and streams, tile list) differs from the one it was built for
+    std::vector<int64_t>& key = ctx->layout_key;
+    const size_t klen = 2 + 2 * static_cast<size_t>(a.n_sets) + (tiles ? 3 * static_cast<size_t>(d->n_tiles) : 0);
+    bool same = ctx->layout_valid && key.size() == klen && key[0] == a.n_sets && key[1] == (tiles ? d->n_tiles : -1);
+    for (int i = 0; same && i < a.n_sets; ++i)
+        same = key[2 + 2 * i] == a.sets[i].n && key[3 + 2 * i] == a.sets[i].stream;
+    if (same && tiles)
+        same = std::memcmp(key.data() + 2 + 2 * a.n_sets, tiles, sizeof(int64_t) * 3 * d->n_tiles) == 0;
+    if (!same) {
+        ctx->layout_valid = false;
+        if (tiles) {
+            r = stage_tiles(ctx, tiles, d->n_tiles, s);
+            if (r) return r;
+        }
+        ChunkBuildArgs b = chunk_build_args(a, plan);
+        b.tiles = tiles ? ctx->d_tiles : nullptr;
+        b.order = ctx->d_part;
+        b.ostart = ctx->d_part + ctx->tiles_cap;
+        b.chunks = ctx->d_chunks;
+        const hipError_t e = launch_chunk_build(b, s);
+        if (e != hipSuccess) return hip_fail(e, "chunk table build");
+        key.assign(klen, 0);
+        key[0] = a.n_sets;
+        key[1] = tiles ? d->n_tiles : -1;
+        for (int i = 0; i < a.n_sets; ++i) {
+            key[2 + 2 * i] = a.sets[i].n;
+            key[3 + 2 * i] = a.sets[i].stream;
+        }
+        if (tiles) std::memcpy(key.data() + 2 + 2 * a.n_sets, tiles, sizeof(int64_t) * 3 * d->n_tiles);
+        ctx->layout_valid = true;
+    }
+    a.n_chunks = plan.n_chunks;
+    const int grid = std::max(1, std::min(a.n_chunks, cached_grid(ctx, a, dtype)));
+    ctx->epoch = ctx->epoch + 1 == 0 ? 1 : ctx->epoch + 1;
+    a.status = ctx->d_status;
+    a.ticket = ctx->d_ticket;
+    a.ticket_base = ctx->ticket_issued;
+    a.epoch = ctx->epoch;
+    a.chunks = ctx->d_chunks;
+    const hipError_t e = launch_step(a, dtype, grid, s);
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    // every block takes exactly one failing ticket before it exits
+    ctx->ticket_issued += static_cast<unsigned long long>(a.n_chunks) + static_cast<unsigned long long>(grid);
+    return QED_OK;
 }
 
 extern "C" int32_t qed_step(qed_context* ctx, const qed_step_desc* d, void* stream) {

@@ -110,12 +110,34 @@ struct ElemArgs {
     Units units;
 };
 
+// Chunk table construction on the device (chunks.hip).  The host has
+// validated the tiles and counted the chunks; `order` / `ostart` are device
+// scratch of n_part entries each.
+struct ChunkBuildArgs {
+    const int64_t* tiles;        // device, 3 * n_tiles; NULL: one tile per set
+    int32_t n_tiles;             // tiles (sets when `tiles` is NULL)
+    int32_t n_part0;             // tiles of stream 0 holding at least one chunk
+    int32_t n_part;              // ... of both streams
+    int32_t n_chunks0;           // chunks of stream 0 (they come first)
+    int32_t n_chunks;
+    int32_t set_stream[kMaxSets];
+    int64_t set_n[kMaxSets];
+    int32_t* order;              // tile index by position in its stream
+    int32_t* ostart;             // first chunk of that tile
+    ChunkDesc* chunks;           // n_chunks entries
+};
+hipError_t launch_chunk_build(const ChunkBuildArgs& a, hipStream_t s);
+// Copy host tiles to device memory through kernel arguments (no staging
+// buffer, no allocation): one small launch per 160 tiles.
+hipError_t store_tiles_by_args(const int64_t* host_tiles, int n_tiles, int64_t* dst, hipStream_t s);
+
 // Kernel launchers (step.hip).  Return hipError_t of the launch.
 hipError_t launch_step(const StepArgs& a, int dtype, int grid, hipStream_t s);
 hipError_t launch_chi(const ElemArgs& a, int dtype, hipStream_t s);
 hipError_t launch_init_tau(const ElemArgs& a, int dtype, hipStream_t s);
 hipError_t launch_evolve(const ElemArgs& a, int dtype, hipStream_t s);
 int step_grid_size(const StepArgs& a, int dtype, int device);
+size_t step_lds_bytes_for(const StepArgs& a, int dtype);
 
 struct TableCallArgs {
     TableDev table;
@@ -154,7 +176,27 @@ struct qed_context {
     uint32_t epoch = 0;
     qedmi::ChunkDesc* d_chunks = nullptr;
     int64_t chunks_cap = 0;
-    std::vector<qedmi::ChunkDesc> h_chunks_cached;
+    // device tile list and chunk-builder scratch (order, ostart)
+    int64_t* d_tiles = nullptr;
+    int32_t* d_part = nullptr;
+    int64_t tiles_cap = 0;
+    // pinned host staging of the tile list, double-buffered: buffer i is
+    // rewritten only after the copy issued from it two calls earlier is done
+    int64_t* h_stage[2] = {nullptr, nullptr};
+    hipEvent_t stage_ev[2] = {nullptr, nullptr};
+    int64_t stage_cap = 0;
+    int stage_next = 0;
+    // layout of the chunk table now on the device (skip the rebuild when unchanged)
+    bool layout_valid = false;
+    std::vector<int64_t> layout_key;
+    std::vector<int32_t> tile_idx;          // host scratch of the tile overlap check
+    // persistent grid per step-kernel variant (dtype, surrogate, chi mode, LDS bytes)
+    struct GridCache {
+        int dtype, surr, chi_mode;
+        size_t lds;
+        int grid;
+    };
+    std::vector<GridCache> grids;
     void* d_scratch = nullptr;              // general device scratch (Schwinger scan offsets)
     int64_t scratch_cap = 0;                // bytes
     qedmi::Units units;                     // caller unit system (qed_context_set_units)
@@ -167,4 +209,22 @@ AppendDev append_view(const qed_append* a);
 int32_t reserve_scratch(qed_context* ctx, int64_t bytes);
 // Table generation on the current device (tablegen_device.hip); fills host arrays.
 int32_t generate_tables_device(const qed_table_params& p, double* ln_rate, double* cdf, hipStream_t stream);
+
+// Fused-step preparation shared by qed_step and its allocation-free variant.
+struct ChunkPlan {
+    int32_t n_tiles;        // tiles (sets when the caller gave none)
+    int32_t n_part0, n_part;
+    int32_t n_chunks0, n_chunks;
+};
+// Validate a step descriptor and fill the kernel arguments, in two parts:
+// the particle sets (no HIP call), then tables, append buffers and
+// surrogates.  The chunk table, look-back scratch and ticket are left for
+// the caller.  No allocation.
+int32_t prepare_sets(const qed_step_desc* d, bool generate_only, StepArgs& a, int& dtype);
+int32_t prepare_tables(const Units& units, const qed_step_desc* d, StepArgs& a, int dtype);
+// Validate the tiles (each inside its set, disjoint within a set) and
+// count chunks per stream.  `idx` is host scratch of n_tiles entries, used
+// only when a set's tiles are not in increasing order.  No allocation.
+int32_t plan_chunks(const StepArgs& a, const int64_t* tiles, int32_t n_tiles, int32_t* idx, ChunkPlan& plan);
+ChunkBuildArgs chunk_build_args(const StepArgs& a, const ChunkPlan& plan);
 }  // namespace qedmi

@@ -250,6 +250,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     // (one atomic per counter and block instead of one per chunk or batch)
     unsigned long long n_updates = 0, n_qs_events = 0, n_bw_events = 0, n_kept = 0;
     unsigned long long n_surr_batches = 0, n_surr_fallbacks = 0;   // lane 0 of each wave
+    unsigned n_nonfinite = 0;   // per thread: chi not finite, or tau NaN or -inf
 
     for (;;) {
         __syncthreads();
@@ -343,6 +344,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                             if (!photon)
                                 classical_drag<T>(S, j, v[b][0], v[b][1], v[b][2], chi, a.drag, a.units.inv_u);
                         }
+                        // +inf is a decayed photon's optical depth, not an error
+                        constexpr T kBig = sizeof(T) == 8 ? T(1.7976931348623157e308) : T(3.40282347e38f);
+                        n_nonfinite += !(chi <= kBig) || !(tn >= -kBig);
                         if (ev) s_chi[loc] = chi;
                         else stnt<T>(S.p[9], j, tn);
                         if (S.flags) S.flags[j] = static_cast<uint8_t>(ev);
@@ -601,6 +605,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             add(QED_STAT_SURR_BATCHES, n_surr_batches);
             add(QED_STAT_SURR_FALLBACK, n_surr_fallbacks);
         }
+        add(QED_STAT_NONFINITE, n_nonfinite);
     }
 }
 
@@ -735,6 +740,8 @@ int elem_grid(int64_t n) {
 }
 
 }  // namespace
+
+size_t step_lds_bytes_for(const StepArgs& a, int dtype) { return step_lds_bytes(a, dtype == QED_FP64 ? 8 : 4); }
 
 hipError_t launch_step(const StepArgs& a, int dtype, int grid, hipStream_t s) {
     if (dtype == QED_FP64) return launch_step_t<double, false>(a, grid, s);

@@ -200,6 +200,92 @@ def test_tiles_follow_tile_order(ctx, tabs):
     _run_steps(ctx, tabs, n, n, 2, seed=4, tiles=tiles)
 
 
+def _random_layout(rng, n_e, n_g, pieces=5):
+    """Each set cut at random points into `pieces` tiles, all tiles shuffled."""
+    tl = []
+    for si, n in ((0, n_e), (1, n_g)):
+        cuts = sorted(rng.choice(np.arange(1, n), pieces - 1, replace=False).tolist())
+        edges = [0, *cuts, n]
+        tl += [(si, int(a), int(b)) for a, b in zip(edges[:-1], edges[1:])]
+    order = rng.permutation(len(tl))
+    return [tl[i] for i in order]
+
+
+def test_tile_layout_changes_every_step_without_sync(ctx, tabs):
+    """A new tile list every step (cut points and tile order, hence product
+    order, change), the steps queued back to back with no host
+    synchronisation between them: the tile list reaches the device through
+    pinned double-buffered staging and the chunk table is built there.  The
+    products of all steps, the final state and the last flags match the
+    oracle run over the same tile lists."""
+    (bw, qs), (obw, oqs) = tabs
+    n, steps, seed, dt = 20000, 6, 21, 1e-16
+    rng = np.random.default_rng(5)
+    layouts = [_random_layout(rng, n, n) for _ in range(steps)]
+    el, ph = QI.parity_population(seed=seed, n=n)
+    oe, og = O.Particles(el, O.ELECTRON, id_base=0), O.Particles(ph, O.PHOTON, id_base=1 << 40)
+    O.init_optical_depth(oe, seed)
+    O.init_optical_depth(og, seed)
+    de, dg = dev_pop(el, torch.float64, tau=oe["tau"]), dev_pop(ph, torch.float64, tau=og["tau"])
+    pe, pg = Q.particles(de, Q.ELECTRON, 0), Q.particles(dg, Q.PHOTON, 1 << 40)
+    cap = steps * n
+    bufs = [Q.AppendBuffer(cap, torch.float64) for _ in range(3)]
+    orc = [O.Append(cap) for _ in range(3)]
+    fe = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    fg = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    u0 = [np.sqrt(o["ux"] ** 2 + o["uy"] ** 2 + o["uz"] ** 2) for o in (oe, og)]
+    for s in range(steps):
+        desc = Q.StepDesc([pe, pg], bw=bw, qs=qs, photons=bufs[0], electrons=bufs[1], positrons=bufs[2],
+                          flags=[fe, fg], tiles=layouts[s], dt=dt, seed=seed, step=s)
+        Q.step(ctx, desc)
+    ofe, ofg = np.zeros(n, dtype=np.uint8), np.zeros(n, dtype=np.uint8)
+    for s in range(steps):
+        _oracle_tiles(obw, oqs, [oe, og], layouts[s], dt, seed, s, orc[0], orc[1], orc[2], 0.0, [ofe, ofg])
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(fe.cpu().numpy(), ofe)
+    np.testing.assert_array_equal(fg.cpu().numpy(), ofg)
+    assert orc[0].count > 1000 and orc[1].count > 10
+    for b, o, what, os_ in zip(bufs, orc, ("photons", "electrons", "positrons"), (oe, og, og)):
+        par = o.parent[:o.count] - os_.id_base
+        compare_append(b, o, RTOL, what, (u0[0] if os_ is oe else u0[1])[par])
+    for d, o, um in ((de, oe, u0[0]), (dg, og, u0[1])):
+        fin = np.isfinite(o["tau"])
+        assert np.array_equal(np.isinf(host(d["tau"])), ~fin)
+        assert rel_close(host(d["tau"])[fin], o["tau"][fin], RTOL) <= 1.0
+        for k in ("ux", "uy", "uz"):
+            assert rel_close(host(d[k]), o[k], RTOL, floor=np.maximum(um, 1e-300)) <= 1.0
+
+
+def test_nonfinite_inputs_are_counted(ctx, tabs):
+    """NaN or infinite momenta and fields give a non-finite chi, and a NaN or
+    -inf optical depth a non-finite update: each such particle is counted in
+    the NONFINITE statistic.  A decayed photon (tau = +inf) is not."""
+    (bw, qs), _ = tabs
+    n, seed = 5000, 3
+    el, ph = QI.parity_population(seed=seed, n=n)
+    el["ux"][5] = np.nan
+    el["ey"][7] = np.inf
+    el["bz"][8] = -np.inf
+    ph["bz"][11] = np.nan
+    te = np.full(n, 0.5)
+    tg = np.full(n, 0.5)
+    te[9] = np.nan
+    te[10] = -np.inf
+    tg[20] = np.inf            # a photon that decayed earlier
+    de, dg = dev_pop(el, torch.float64, tau=te), dev_pop(ph, torch.float64, tau=tg)
+    pe, pg = Q.particles(de, Q.ELECTRON, 0), Q.particles(dg, Q.PHOTON, 1 << 40)
+    bufs = [Q.AppendBuffer(2 * n, torch.float64) for _ in range(3)]
+    stats = torch.zeros(Q.STATS_LEN, dtype=torch.int64, device="cuda")
+    desc = Q.StepDesc([pe, pg], bw=bw, qs=qs, photons=bufs[0], electrons=bufs[1], positrons=bufs[2],
+                      stats=stats, dt=1e-16, seed=seed)
+    Q.step(ctx, desc)
+    st = stats.cpu().numpy()
+    assert st[Q.STAT_NONFINITE] == 6, st
+    assert st[Q.STAT_UPDATES] == 2 * n
+    assert st[Q.STAT_SCAN_TIMEOUT] == 0
+    assert np.isinf(host(dg["tau"])[20])
+
+
 def test_tiles_with_odd_boundaries(ctx, tabs):
     """Tiles starting at odd indices (the streaming phase falls back from
     16-byte loads to one element per load) and ragged tile ends."""

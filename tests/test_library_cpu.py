@@ -102,3 +102,42 @@ def test_null_arguments_are_refused_without_launch():
     assert L.qed_context_create(0, None) == Q.QED_ERR_INVALID
     assert L.qed_schwinger_rate(None, None, None, None) == Q.QED_ERR_INVALID
     assert L.qed_schwinger_pairs(None, None, 1.0, 1.0, 1.0, 0, 0, None, None, None) == Q.QED_ERR_INVALID
+
+
+def _desc_with_tiles(n, tiles, species=Q.ELECTRON):
+    """A step descriptor over one set of n particles whose array pointers are
+    dummies: the calls below are refused before anything touches them."""
+    dummy = 1 << 20
+    p = (Q.ParticlesC * 1)(Q.ParticlesC(*([dummy] * 11), n, 0, species, Q.FP64))
+    t = np.ascontiguousarray(np.asarray(tiles, dtype=np.int64).reshape(-1))
+    d = Q.StepDescC()
+    d.sets = p
+    d.n_sets = 1
+    d.n_tiles = len(t) // 3
+    d.tiles = t.ctypes.data_as(C.POINTER(C.c_int64))
+    d.dt = 1e-16
+    return d, (p, t)
+
+
+def _refusal(tiles, n=1000):
+    d, keep = _desc_with_tiles(n, tiles)
+    rc = Q.lib().qed_step(None, C.byref(d), None)
+    del keep
+    return rc, Q.lib().qed_last_error().decode()
+
+
+def test_tile_overlap_is_refused_before_launch():
+    """Tiles of one set must be disjoint (an overlapping particle would be
+    stepped twice).  The check is on the host, before the first HIP call and
+    before the context is looked at, so it runs here without a GPU; tiles
+    out of order but disjoint pass it and stop at the next check (the
+    missing context)."""
+    rc, msg = _refusal([(0, 0, 600), (0, 500, 1000)])
+    assert rc == Q.QED_ERR_INVALID and "overlap" in msg
+    rc, msg = _refusal([(0, 600, 1000), (0, 0, 300), (0, 250, 600)])     # out of order and overlapping
+    assert rc == Q.QED_ERR_INVALID and "overlap" in msg
+    rc, msg = _refusal([(0, 0, 1001)])
+    assert rc == Q.QED_ERR_INVALID and "out of range" in msg
+    rc, msg = _refusal([(0, 600, 1000), (0, 0, 300), (0, 300, 600), (0, 300, 300)])   # disjoint, shuffled, one empty
+    assert rc == Q.QED_ERR_INVALID and "context" in msg
+
