@@ -316,6 +316,27 @@ enum {
 
 int32_t qed_step(qed_context* ctx, const qed_step_desc* desc, void* stream);
 
+/* qed_step for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same descriptor, kernels and results as qed_step (bit-identical), but
+ * every scratch buffer (chunk ticket, look-back status words, chunk table,
+ * tile list) lives in one fixed library array per GPU of 2.81 MiB, held
+ * until the process ends; nothing is allocated, on the device or the host,
+ * and the host is never synchronised.
+ *   ctx     may be NULL (SI units, current device); when given, only its
+ *           unit system and device are used, never its scratch.
+ *   limits  at most 65536 chunks of 4096 particles (2^28 particles over
+ *           all sets, counted per tile) and at most 8192 tiles; larger
+ *           inputs return QED_ERR_INVALID before anything is launched.
+ *   sharing every call on one GPU uses that GPU's array: calls that overlap
+ *           on one GPU (different streams or threads) race.  Calls ordered
+ *           on one stream are safe; the array needs no clearing between
+ *           them (the ticket is monotonic, status words carry a per-call
+ *           epoch and the chunk table is rebuilt by every call).
+ * Each call re-uploads the tile list through kernel arguments (one small
+ * launch per 160 tiles) and rebuilds the chunk table on the device. */
+int32_t qed_step_noalloc(const qed_context* ctx, const qed_step_desc* desc, void* stream);
+
 /* Synchronise `stream` and read an append buffer's count to the host;
  * returns QED_ERR_CAPACITY if it exceeds the buffer's capacity. */
 int32_t qed_read_count(const qed_append* a, int64_t* host_count, void* stream);

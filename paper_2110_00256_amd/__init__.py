@@ -30,7 +30,7 @@ EXPORTS = (
     "qed_table_host_data", "qed_table_to_device", "qed_table_destroy", "qed_table_generate_device",
     "qed_context_create", "qed_context_destroy", "qed_context_set_units",
     "qed_chi_lepton", "qed_chi_photon", "qed_init_optical_depth", "qed_evolve_optical_depth",
-    "qed_generate_pairs", "qed_generate_photon_and_update_momentum", "qed_step", "qed_read_count",
+    "qed_generate_pairs", "qed_generate_photon_and_update_momentum", "qed_step", "qed_step_noalloc", "qed_read_count",
     "qed_table_rate", "qed_table_sample",
     "qed_surrogate_train", "qed_surrogate_from_host", "qed_surrogate_get_params",
     "qed_surrogate_forward", "qed_surrogate_grad", "qed_surrogate_sample", "qed_surrogate_destroy",
@@ -126,6 +126,7 @@ def lib():
             "qed_generate_photon_and_update_momentum": [vp, vp, P(ParticlesC), vp, u64, u64, i32, d,
                                                         P(AppendC), vp],
             "qed_step": [vp, P(StepDescC), vp],
+            "qed_step_noalloc": [vp, P(StepDescC), vp],
             "qed_read_count": [P(AppendC), P(i64), vp],
             "qed_table_rate": [vp, i32, vp, vp, vp, i64, vp],
             "qed_table_sample": [vp, i32, vp, vp, vp, vp, i64, vp],
@@ -374,6 +375,12 @@ class StepDesc:
 
 def step(ctx, desc: StepDesc, stream=None):
     check(lib().qed_step(ctx.h, C.byref(desc.c), _stream(stream)))
+
+
+def step_noalloc(ctx, desc: StepDesc, stream=None):
+    """qed_step_noalloc: the same step with the library's fixed per-GPU
+    scratch (ctx may be None: SI units, current device)."""
+    check(lib().qed_step_noalloc(ctx.h if ctx is not None else None, C.byref(desc.c), _stream(stream)))
 
 
 def version():

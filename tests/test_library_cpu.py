@@ -96,6 +96,7 @@ def test_invalid_table_params(kw):
 def test_null_arguments_are_refused_without_launch():
     L = Q.lib()
     assert L.qed_step(None, None, None) == Q.QED_ERR_INVALID
+    assert L.qed_step_noalloc(None, None, None) == Q.QED_ERR_INVALID
     assert L.qed_chi_lepton(None, None, 0, None, None) == Q.QED_ERR_INVALID
     assert L.qed_read_count(None, None, None) == Q.QED_ERR_INVALID
     assert L.qed_table_to_device(None, None) == Q.QED_ERR_INVALID
@@ -141,3 +142,19 @@ def test_tile_overlap_is_refused_before_launch():
     rc, msg = _refusal([(0, 600, 1000), (0, 0, 300), (0, 300, 600), (0, 300, 300)])   # disjoint, shuffled, one empty
     assert rc == Q.QED_ERR_INVALID and "context" in msg
 
+
+
+def test_noalloc_limits_are_refused_before_launch():
+    """qed_step_noalloc's fixed scratch holds 8192 tiles and 65536 chunks of
+    4096 particles; beyond either the call is refused with a message, before
+    any HIP call (so this runs without a GPU)."""
+    for tiles, n, what in (([(0, i, i + 1) for i in range(8193)], 8193, "8192 tiles"),
+                           ([(0, 0, (1 << 28) + 1)], (1 << 28) + 1, "65536 chunks")):
+        d, keep = _desc_with_tiles(n, tiles)
+        assert Q.lib().qed_step_noalloc(None, C.byref(d), None) == Q.QED_ERR_INVALID
+        assert what in Q.lib().qed_last_error().decode()
+        del keep
+    # an overlap is refused the same way as by qed_step
+    d, keep = _desc_with_tiles(1000, [(0, 0, 600), (0, 500, 1000)])
+    assert Q.lib().qed_step_noalloc(None, C.byref(d), None) == Q.QED_ERR_INVALID
+    assert "overlap" in Q.lib().qed_last_error().decode()
