@@ -24,6 +24,9 @@ import time
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+# surrogate bands whose largest CDF-space error against the table exceeds
+# this are sampled by the table (KS gate 1e-3 less a margin)
+SURR_KS_BUDGET = 8e-4
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
@@ -232,8 +235,10 @@ def fullstep(Q, torch, QI, args):
     del pops
     log("fullstep: training surrogates")
     t0 = time.perf_counter()
-    sq, lq = Q.Surrogate.train(ctx, qs, Q.Surrogate.cfg(Q.QS, 1e-3, 1e3, n_samples=1 << 22, steps=20000))
-    sb, lb = Q.Surrogate.train(ctx, bw, Q.Surrogate.cfg(Q.BW, 1e-3, 1e3, n_samples=1 << 22, steps=20000))
+    sq, lq = Q.Surrogate.train(ctx, qs, Q.Surrogate.cfg(Q.QS, 1e-3, 1e3, n_samples=1 << 24, steps=args.surrogate_steps,
+                                                        tail_permille=500, ks_budget=SURR_KS_BUDGET))
+    sb, lb = Q.Surrogate.train(ctx, bw, Q.Surrogate.cfg(Q.BW, 1e-3, 1e3, n_samples=1 << 24, steps=args.surrogate_steps,
+                                                        tail_permille=500, ks_budget=SURR_KS_BUDGET))
     train_s = time.perf_counter() - t0
     out = {"workload": "fullstep: 4 x 2^%d particles (e-, e+, photons, ions passthrough), 4096 lognormal tiles, "
                        "Gaussian pulse a0=500 w0=2um, FP32, dt %.3e s" % (int(np.log2(n)), dt),
@@ -506,10 +511,14 @@ def main():
         log("bench: training BW and QS surrogates on the device (chi in [1e-3, 1e3])")
         t0 = time.perf_counter()
         sb, lb = Q.Surrogate.train(ctx, tables[0], Q.Surrogate.cfg(Q.BW, 1e-3, 1e3, n_samples=1 << 24,
-                                                                   steps=args.surrogate_steps))
+                                                                   steps=args.surrogate_steps, tail_permille=500,
+                                                                   ks_budget=SURR_KS_BUDGET))
         sq, lq = Q.Surrogate.train(ctx, tables[1], Q.Surrogate.cfg(Q.QS, 1e-3, 1e3, n_samples=1 << 24,
-                                                                   steps=args.surrogate_steps))
-        train = {"seconds": time.perf_counter() - t0, "steps": args.surrogate_steps, "final_loss": {"bw": lb, "qs": lq}}
+                                                                   steps=args.surrogate_steps, tail_permille=500,
+                                                                   ks_budget=SURR_KS_BUDGET))
+        served = {k: float(np.mean([(s.bands()[1] >> b) & 1 for b in range(64)])) for k, s in (("bw", sb), ("qs", sq))}
+        train = {"seconds": time.perf_counter() - t0, "steps": args.surrogate_steps, "final_loss": {"bw": lb, "qs": lq},
+                 "ks_budget": SURR_KS_BUDGET, "served_band_fraction": served}
         log("bench: FP32 + surrogate path")
         rs = run_path(Q, torch, ctx, tables, pops, "f32", args.steps, args.warmup, dt, Q.CHI_FP64,
                       surrogates=(sb, sq))

@@ -362,6 +362,22 @@ typedef struct {
     uint64_t seed;
     int32_t probe_every;    /* in the fused step, probe one wave batch in
                                this many (1 = every batch; <= 0 means 1)   */
+    int32_t tail_permille;  /* training samples (in 1/1000) whose uniform is
+                               drawn evenly in the network's second input
+                               (logit u for QS, the normal quantile of the
+                               folded r for BW) instead of evenly in u: more
+                               of the set in the tails, where the fit's
+                               largest CDF errors sit.  0: all even in u   */
+    float ks_budget;        /* > 0: after training, the trained chi range is
+                               split into QED_SURR_BANDS equal bands in
+                               ln chi and the network serves a band only if
+                               its largest CDF-space error against the table
+                               there, max over u of |P_table(network sample)
+                               - u| (the KS distance of the two sampled
+                               spectra for a monotone map), stays within
+                               ks_budget on 8 chi x 4096 u validation points;
+                               the table serves the other bands.  0: the
+                               network serves the whole trained range      */
     int32_t pad_;
 } qed_surrogate_cfg;
 
@@ -377,6 +393,11 @@ int32_t qed_surrogate_from_host(const qed_table* table, const qed_surrogate_cfg*
  * W2[64][64] (row = output unit), b2[64], W3[64], b3. */
 enum { QED_SURR_NPARAM = 64 * 2 + 64 + 64 * 64 + 64 + 64 + 1 };
 int32_t qed_surrogate_get_params(const qed_surrogate* s, float* host_params);
+/* The validation result: band_err (host, QED_SURR_BANDS floats) receives
+ * each band's largest CDF-space error (0 if not validated), *served_mask
+ * bit b is set when band b is sampled by the network. */
+enum { QED_SURR_BANDS = 64 };
+int32_t qed_surrogate_bands(const qed_surrogate* s, float* band_err, uint64_t* served_mask);
 /* Forward on n device inputs x[n][2] (FP32) -> y[n] (FP32), BF16 MFMA. */
 int32_t qed_surrogate_forward(const qed_surrogate* s, const float* x, float* y, int64_t n, void* stream);
 /* Loss and gradient of 0.5 mean((y - t)^2) over one minibatch of device

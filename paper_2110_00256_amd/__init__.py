@@ -32,7 +32,7 @@ EXPORTS = (
     "qed_chi_lepton", "qed_chi_photon", "qed_init_optical_depth", "qed_evolve_optical_depth",
     "qed_generate_pairs", "qed_generate_photon_and_update_momentum", "qed_step", "qed_step_noalloc", "qed_read_count",
     "qed_table_rate", "qed_table_sample",
-    "qed_surrogate_train", "qed_surrogate_from_host", "qed_surrogate_get_params",
+    "qed_surrogate_train", "qed_surrogate_from_host", "qed_surrogate_get_params", "qed_surrogate_bands",
     "qed_surrogate_forward", "qed_surrogate_grad", "qed_surrogate_sample", "qed_surrogate_destroy",
     "qed_schwinger_rate", "qed_schwinger_pairs", "qed_push",
     "qed_last_error", "qed_version",
@@ -93,7 +93,8 @@ class SurrogateCfg(C.Structure):
     _fields_ = [("process", C.c_int32), ("n_samples", C.c_int32), ("batch", C.c_int32),
                 ("steps", C.c_int32), ("lr", C.c_float), ("probe_tol", C.c_float),
                 ("chi_lo", C.c_double), ("chi_hi", C.c_double), ("seed", C.c_uint64),
-                ("probe_every", C.c_int32), ("pad_", C.c_int32)]
+                ("probe_every", C.c_int32), ("tail_permille", C.c_int32),
+                ("ks_budget", C.c_float), ("pad_", C.c_int32)]
 
 
 _lib = None
@@ -133,6 +134,7 @@ def lib():
             "qed_surrogate_train": [vp, vp, P(SurrogateCfg), P(vp), P(C.c_float), vp],
             "qed_surrogate_from_host": [vp, P(SurrogateCfg), vp, P(vp)],
             "qed_surrogate_get_params": [vp, vp],
+            "qed_surrogate_bands": [vp, vp, P(u64)],
             "qed_surrogate_forward": [vp, vp, vp, i64, vp],
             "qed_surrogate_grad": [vp, vp, vp, i64, vp, vp, vp],
             "qed_surrogate_sample": [vp, vp, vp, vp, i64, vp],
@@ -397,8 +399,9 @@ class Surrogate:
 
     @staticmethod
     def cfg(process, chi_lo, chi_hi, n_samples=1 << 22, batch=16384, steps=20000, lr=3e-3, probe_tol=0.5,
-            seed=7, probe_every=16):
-        return SurrogateCfg(process, n_samples, batch, steps, lr, probe_tol, chi_lo, chi_hi, seed, probe_every, 0)
+            seed=7, probe_every=16, tail_permille=0, ks_budget=0.0):
+        return SurrogateCfg(process, n_samples, batch, steps, lr, probe_tol, chi_lo, chi_hi, seed, probe_every,
+                            tail_permille, ks_budget, 0)
 
     @classmethod
     def train(cls, ctx, table, cfg, stream=None):
@@ -415,6 +418,14 @@ class Surrogate:
         h = C.c_void_p()
         check(lib().qed_surrogate_from_host(table.h, C.byref(cfg), p.ctypes.data, C.byref(h)))
         return cls(h.value, table)
+
+    def bands(self):
+        """(per-band largest CDF-space error, served-band mask)."""
+        import numpy as np
+        err = np.zeros(64, dtype=np.float32)
+        mask = C.c_uint64()
+        check(lib().qed_surrogate_bands(self.h, err.ctypes.data, C.byref(mask)))
+        return err, mask.value
 
     def params(self):
         import numpy as np

@@ -24,6 +24,9 @@ struct qed_surrogate {
     float* d_m = nullptr;        // Adam first moment
     float* d_v = nullptr;        // Adam second moment
     uint16_t* d_w2 = nullptr;    // BF16 copy of W2
+    unsigned long long band_mask = ~0ULL;   // bands the network serves (all until validated)
+    float band_err[kSurrBands] = {};        // largest CDF-space error found per band
+    bool validated = false;
     SurrogateDev view() const {
         SurrogateDev s{};
         s.p = d_p;
@@ -36,6 +39,9 @@ struct qed_surrogate {
         s.chi_hi = static_cast<float>(cfg.chi_hi);
         s.probe_tol = cfg.probe_tol;
         s.probe_every = cfg.probe_every > 0 ? cfg.probe_every : 1;
+        s.band_mask = band_mask;
+        s.ln_chi_lo = static_cast<float>(l0);
+        s.band_inv_w = static_cast<float>(kSurrBands / (l1 - l0));
         return s;
     }
 };
@@ -63,14 +69,27 @@ __device__ __forceinline__ double surr_target(const TableDev& t, int process, do
 }
 
 __global__ void __launch_bounds__(256) surr_make_set(TableDev t, SurrogateDev s, unsigned long long seed, int n,
-                                                     double ln_lo, double ln_hi, float4* out) {
+                                                     double ln_lo, double ln_hi, double tail_frac, float4* out) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const dev::Draws d = dev::draws(seed, static_cast<unsigned long long>(i), kTrainStep,
                                         static_cast<unsigned long long>(s.process), 0ULL);
         const double chi = exp(ln_lo + (ln_hi - ln_lo) * d.u[0]);
         double u;
-        if (s.process == 1) u = kSurrUMin + (static_cast<double>(kSurrUMaxQs) - kSurrUMin) * d.u[1];
-        else u = kSurrUMin + (0.5 - kSurrUMin) * d.u[1];
+        if (d.u[2] < tail_frac) {
+            // even in the network's second input x1 over [-1, 1]
+            const double x1 = 2.0 * d.u[1] - 1.0;
+            if (s.process == 1) {
+                const double logit = kSurrLogitMid + x1 / kSurrLogitInvHalf;
+                u = fmin(fmax(1.0 / (1.0 + exp(-logit)), kSurrUMin), static_cast<double>(kSurrUMaxQs));
+            } else {
+                const double q = 0.5 * (x1 - 1.0) * kBwQMin;          // Phi^{-1}(r) in [-qmin, 0]
+                u = fmin(fmax(0.5 * erfc(-q * 0.70710678118654752), kSurrUMin), 0.5);
+            }
+        } else if (s.process == 1) {
+            u = kSurrUMin + (static_cast<double>(kSurrUMaxQs) - kSurrUMin) * d.u[1];
+        } else {
+            u = kSurrUMin + (0.5 - kSurrUMin) * d.u[1];
+        }
         const double tgt = surr_target(t, s.process, chi, u);
         // slope of the sampled quantity itself (QS: ln Y = target + 3 ln u;
         // BW: the target is linear in xi), so that w (dy)^2 = (du)^2
@@ -334,6 +353,76 @@ __global__ void __launch_bounds__(256) surr_forward_kernel(SurrogateDev s, const
     }
 }
 
+// The table's cumulative distribution at a sample (QS: ln xi; BW: xi in
+// [0, 1/2]) for the row interpolated at chi, in FP64: the exact inverse of
+// the table sampler (rows interpolated in ln chi, then linear in ln xi for
+// QS with the small-xi law below the first knot, linear in xi for BW).
+__device__ double table_cdf_at(const TableDev& t, int process, double chi, double sample) {
+    int n;
+    double f;
+    dev::row_pos<double>(t, chi, n, f);
+    const int nf = t.n_frac;
+    const double* pp = t.cdf64 + 2 * static_cast<size_t>(n) * nf;
+    if (process == 1) {
+        const double lmin = t.ln_frac_min;
+        const double x = (sample - lmin) * (nf - 1) / (-lmin);
+        if (x < 0.0) return exp(dev::pair_value<double, double>(pp, f, 0) + (sample - lmin) / 3.0);
+        if (x >= nf - 1) return 1.0;
+        const int m = static_cast<int>(x);
+        const double la = dev::pair_value<double, double>(pp, f, m), lb = dev::pair_value<double, double>(pp, f, m + 1);
+        return exp(la + (x - m) * (lb - la));
+    }
+    const double x = fmin(fmax(sample, 0.0), 0.5) * (nf - 1) / 0.5;
+    const int m = min(static_cast<int>(x), nf - 2);
+    const double pa = dev::pair_value<double, double>(pp, f, m), pb = dev::pair_value<double, double>(pp, f, m + 1);
+    return pa + (x - m) * (pb - pa);
+}
+
+constexpr int kValChiPerBand = 8;   // chi points per band, both band edges included
+constexpr int kValU = 4096;         // uniforms per chi point: half even in x1, half even in u
+
+// Validation: for each (band, chi point) block, the largest |F_table(network
+// sample) - u| over kValU uniforms of the network's domain.  For a monotone
+// map this is the Kolmogorov-Smirnov distance between the network's and the
+// table's sampled spectra at that chi.  Block maxima go to band_err (as
+// ordered bit patterns of non-negative floats).
+__global__ void __launch_bounds__(256) surr_validate_kernel(SurrogateDev s, TableDev t, double ln_lo, double ln_hi,
+                                                            unsigned* band_err) {
+    __shared__ float s_max[4];
+    const int band = blockIdx.x / kValChiPerBand, cj = blockIdx.x % kValChiPerBand;
+    const int wave = threadIdx.x >> 6, lane = static_cast<int>(__lane_id());
+    const double lc = ln_lo + (ln_hi - ln_lo) * (band + cj / static_cast<double>(kValChiPerBand - 1)) / kSurrBands;
+    const float chi = fminf(fmaxf(static_cast<float>(exp(lc)), s.chi_lo), s.chi_hi);
+    const double u_hi = s.process == 1 ? static_cast<double>(kSurrUMaxQs) : 0.5;
+    float worst = 0.0f;
+    for (int i0 = wave * 64; i0 < kValU; i0 += 256) {
+        const int i = i0 + lane;
+        double u;
+        if (i < kValU / 2) {
+            const double x1 = -1.0 + 2.0 * (i + 0.5) / (kValU / 2);
+            if (s.process == 1) u = 1.0 / (1.0 + exp(-(kSurrLogitMid + x1 / kSurrLogitInvHalf)));
+            else u = 0.5 * erfc(-0.5 * (x1 - 1.0) * kBwQMin * 0.70710678118654752);
+        } else {
+            u = kSurrUMin + (u_hi - kSurrUMin) * ((i - kValU / 2) + 0.5) / (kValU / 2);
+        }
+        const float uf = fminf(fmaxf(static_cast<float>(u), kSurrUMin), static_cast<float>(u_hi));
+        float x0, x1f;
+        surr_features(s, chi, uf, x0, x1f);
+        const float y = surr_forward_wave(s, x0, x1f);
+        const float smp = surr_output(s, chi, uf, y);
+        const double err = fabs(table_cdf_at(t, s.process, chi, smp) - static_cast<double>(uf));
+        worst = fmaxf(worst, static_cast<float>(err));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) worst = fmaxf(worst, __shfl_xor(worst, o));
+    if (lane == 0) s_max[wave] = worst;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float m = fmaxf(fmaxf(s_max[0], s_max[1]), fmaxf(s_max[2], s_max[3]));
+        atomicMax(band_err + band, __float_as_uint(m));
+    }
+}
+
 // Sampling for (chi, u) arrays: surrogate inside its domain, table outside.
 __global__ void __launch_bounds__(256) surr_sample_kernel(SurrogateDev s, TableDev t, const float* chi, const float* u,
                                                           float* out, long long n) {
@@ -415,6 +504,40 @@ void init_params(std::vector<float>& p, uint64_t seed) {
     for (int i = 0; i < 64; ++i) p[kOffW3 + i] = static_cast<float>(next() * std::sqrt(6.0 / 65.0));
 }
 
+// Validate the network band by band against the table (when the cfg sets a
+// budget): a band is served by the network only if its largest CDF-space
+// error over the validation points is within ks_budget.  Synchronous.
+int32_t validate_bands(qed_surrogate* s, hipStream_t st) {
+    s->band_mask = ~0ULL;
+    s->validated = false;
+    for (float& x : s->band_err) x = 0.f;
+    if (!(s->cfg.ks_budget > 0.f)) return QED_OK;
+    unsigned* d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(unsigned) * kSurrBands);
+    if (e != hipSuccess) { set_error("validation buffer: allocation failed"); return QED_ERR_ALLOC; }
+    e = hipMemsetAsync(d, 0, sizeof(unsigned) * kSurrBands, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(surr_validate_kernel, dim3(kSurrBands * kValChiPerBand), dim3(256), 0, st, s->view(),
+                           s->table, std::log(s->cfg.chi_lo), std::log(s->cfg.chi_hi), d);
+        e = hipGetLastError();
+    }
+    unsigned h[kSurrBands] = {};
+    if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipFree(d);
+    if (e != hipSuccess) return hfail(e, "band validation");
+    unsigned long long mask = 0ULL;
+    for (int b = 0; b < kSurrBands; ++b) {
+        float v;
+        std::memcpy(&v, &h[b], sizeof v);
+        s->band_err[b] = v;
+        if (v <= s->cfg.ks_budget) mask |= 1ULL << b;
+    }
+    s->band_mask = mask;
+    s->validated = true;
+    return QED_OK;
+}
+
 }  // namespace
 
 namespace qedmi {
@@ -455,6 +578,11 @@ extern "C" int32_t qed_surrogate_from_host(const qed_table* table, const qed_sur
     if (e != hipSuccess) {
         qed_surrogate_destroy(s);
         return hfail(e, "surrogate upload");
+    }
+    const int32_t r = validate_bands(s, nullptr);
+    if (r != QED_OK) {
+        qed_surrogate_destroy(s);
+        return r;
     }
     *out = s;
     return QED_OK;
@@ -502,7 +630,8 @@ extern "C" int32_t qed_surrogate_train(qed_context* ctx, const qed_table* table,
     const double ln_lo = std::log(cfg->chi_lo), ln_hi = std::log(cfg->chi_hi);
     const double margin = (ln_hi - ln_lo) / 16.0;
     hipLaunchKernelGGL(surr_make_set, dim3(2048), dim3(256), 0, st, table->view(), v, cfg->seed, cfg->n_samples,
-                       ln_lo - margin, ln_hi + margin, set);
+                       ln_lo - margin, ln_hi + margin, std::min(std::max(cfg->tail_permille, 0), 1000) * 1e-3,
+                       set);
     e = hipGetLastError();
     double b1t = 1.0, b2t = 1.0;
     for (int it = 0; it < cfg->steps && e == hipSuccess; ++it) {
@@ -535,7 +664,19 @@ extern "C" int32_t qed_surrogate_train(qed_context* ctx, const qed_table* table,
         qed_surrogate_destroy(s);
         return hfail(e, "surrogate training");
     }
+    const int32_t rv = validate_bands(s, st);
+    if (rv != QED_OK) {
+        qed_surrogate_destroy(s);
+        return rv;
+    }
     *out = s;
+    return QED_OK;
+}
+
+extern "C" int32_t qed_surrogate_bands(const qed_surrogate* s, float* band_err, uint64_t* served_mask) {
+    if (!s || !band_err || !served_mask) { set_error("surrogate/band_err/served_mask is null"); return QED_ERR_INVALID; }
+    for (int b = 0; b < kSurrBands; ++b) band_err[b] = s->band_err[b];
+    *served_mask = s->band_mask;
     return QED_OK;
 }
 

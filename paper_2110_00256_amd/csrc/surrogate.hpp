@@ -29,6 +29,7 @@ constexpr int kNParam = 64 * 2 + 64 + 64 * 64 + 64 + 64 + 1;   // 4417
 constexpr int kOffW1 = 0, kOffB1 = 128, kOffW2 = 192, kOffB2 = 192 + 4096, kOffW3 = kOffB2 + 64,
               kOffB3 = kOffW3 + 64;
 constexpr float kSurrUMin = 1e-4f;
+constexpr int kSurrBands = 64;
 constexpr float kBwQMin = 3.7190165f;   // -Phi^{-1}(1e-4)
 
 struct SurrogateDev {
@@ -39,6 +40,10 @@ struct SurrogateDev {
     float chi_lo, chi_hi;
     float probe_tol;
     int32_t probe_every;     // probe one wave batch in this many (>= 1)
+    // served bands: the trained range split into kSurrBands equal bands in
+    // ln chi; bit b set: band b is sampled by the network, else by the table
+    unsigned long long band_mask;
+    float ln_chi_lo, band_inv_w;   // b = floor((ln chi - ln_chi_lo) * band_inv_w)
 };
 
 typedef short surr_v4s __attribute__((ext_vector_type(4)));
@@ -87,6 +92,8 @@ __device__ __forceinline__ void surr_features(const SurrogateDev& s, float chi, 
 // Inside the trained domain?  (Otherwise the table is used.)
 __device__ __forceinline__ bool surr_inside(const SurrogateDev& s, float chi, float u) {
     if (!(chi >= s.chi_lo && chi <= s.chi_hi)) return false;
+    const int band = min(kSurrBands - 1, max(0, static_cast<int>((logf(chi) - s.ln_chi_lo) * s.band_inv_w)));
+    if (!((s.band_mask >> band) & 1ULL)) return false;
     if (s.process == 1) return u >= kSurrUMin && u <= kSurrUMaxQs;
     const float r = u <= 0.5f ? u : 1.0f - u;
     return r >= kSurrUMin;

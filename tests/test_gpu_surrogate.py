@@ -79,21 +79,32 @@ def test_gradient_matches_oracle(tables):
     lq, gq = O.mlp_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64), bf16=True)
     l0, g0 = O.mlp_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64), bf16=False)
     assert abs(loss.item() - lq) < 1e-4 * abs(lq)
+    # Element by element against the oracle with the kernel's BF16 operand
+    # rounding emulated.  What remains is FP32 arithmetic: sums of n terms in
+    # fixed order (relative error ~ sqrt(n) 2^-24 of the sum of |terms|), the
+    # hardware exp and reciprocal of SiLU, and the rare hidden activation
+    # whose BF16 rounding the FP32 rounding flips.  Entries that cancel to
+    # near zero are measured against 1e-3 of the group's largest entry.
     for name, sl in (("W1", slice(0, 128)), ("b1", slice(128, 192)), ("W2", slice(192, 4288)),
                      ("b2", slice(4288, 4352)), ("W3", slice(4352, 4416)), ("b3", slice(4416, 4417))):
-        rel_q = np.linalg.norm(g[sl] - gq[sl]) / np.linalg.norm(gq[sl])
+        ref = gq[sl]
+        rel = np.abs(g[sl] - ref) / np.maximum(np.abs(ref), 1e-3 * np.max(np.abs(ref)))
         rel_0 = np.linalg.norm(g[sl] - g0[sl]) / np.linalg.norm(g0[sl])
-        print(f"grad {name}: vs bf16-emulated oracle {rel_q:.2e}, vs FP64 oracle {rel_0:.2e}")
-        assert rel_q < 2e-3, name
+        print(f"grad {name}: per element vs bf16-emulated oracle max {rel.max():.2e} median {np.median(rel):.2e}; "
+              f"norm vs FP64 oracle {rel_0:.2e}")
+        assert rel.max() < 1e-3, name
+        assert np.median(rel) < 1e-5, name
         assert rel_0 < 5e-2, name
 
 
 def _ks_paired(a, b):
-    """sup over a quantile grid of |ECDF_a - ECDF_b| for samples drawn with
-    the same uniforms."""
-    g = np.quantile(b, np.linspace(0.0005, 0.9995, 2000))
+    """Exact two-sample Kolmogorov-Smirnov distance sup_x |ECDF_a - ECDF_b|
+    of two samples of equal size (here drawn with the same uniforms), taken
+    over every value either sample holds, tails included."""
     sa, sb = np.sort(a), np.sort(b)
-    return float(np.max(np.abs(np.searchsorted(sa, g, "right") - np.searchsorted(sb, g, "right")) / len(a)))
+    vals = np.union1d(sa, sb)
+    d = np.abs(np.searchsorted(sa, vals, "right") - np.searchsorted(sb, vals, "right"))
+    return float(d.max() / len(a))
 
 
 @pytest.fixture(scope="module")
@@ -103,26 +114,35 @@ def tables512():
             Q.Table.generate(Q.QS, RANGE[0], RANGE[1], 512, 512).to_device())
 
 
+KS_GATE = 1e-3      # spectrum KS distance the surrogate path must meet
+KS_BUDGET = 8e-4    # per-band validation budget (the gate less a margin for chi between validation points)
+
+
 @pytest.fixture(scope="module")
 def trained(ctx, tables512):
-    """Both surrogates trained on 2^24 samples, 40000 Adam steps of 16384."""
+    """Both surrogates trained on 2^24 samples, 40000 Adam steps of 16384,
+    then validated band by band against the table."""
     out = {}
     for proc in (Q.BW, Q.QS):
         table = tables512[0] if proc == Q.BW else tables512[1]
         cfg = Q.Surrogate.cfg(proc, 1e-3, 1e3, n_samples=1 << 24, batch=16384, steps=40000, lr=3e-3,
-                              probe_tol=1.0)
+                              probe_tol=1.0, tail_permille=500, ks_budget=KS_BUDGET)
         out[proc] = Q.Surrogate.train(ctx, table, cfg)
     return out
 
 
-def _ks_by_chi(s, table, proc, rng):
-    """Paired KS distance between the network's and the table's samples
-    (same uniforms, 2^20 per chi) at chi = 1e-3 ... 1e3."""
-    n = 1 << 20
+CHI_GRID = (1e-3, 3e-3, 1e-2, 3e-2, 0.1, 0.3, 1.0, 3.0, 10.0, 30.0, 100.0, 300.0, 1e3)
+
+
+def _ks_by_chi(s, table, proc, rng, chis=CHI_GRID, n=1 << 21):
+    """Exact paired KS distance between the surrogate path's and the table's
+    sampled spectra (same uniforms, n per chi) at each chi.  QS: the photon's
+    fraction.  BW: the electron's fraction over [0, 1] (Sec. 2.1: the pair
+    spectrum, symmetric about 1/2), i.e. the folded sample xi if u <= 1/2
+    and 1 - xi otherwise; the folded sample alone would count every
+    difference twice."""
     kss = []
-    for chi in (1e-3, 1e-2, 1e-1, 1.0, 10.0, 100.0, 1e3):
-        if proc == Q.BW and chi < 0.05:
-            continue  # pairs are not produced there (T(chi) ~ exp(-8/(3 chi)))
+    for chi in chis:
         u = rng.random(n).astype(np.float32)
         dc = torch.full((n,), chi, dtype=torch.float32, device="cuda")
         du = torch.as_tensor(u).cuda()
@@ -131,24 +151,35 @@ def _ks_by_chi(s, table, proc, rng):
         s.sample(dc, du, out_s)
         Q.table_sample(table, dc, du, out_t)
         torch.cuda.synchronize()
-        ks = _ks_paired(out_s.cpu().numpy(), out_t.cpu().numpy())
+        a, b = out_s.cpu().numpy().astype(np.float64), out_t.cpu().numpy().astype(np.float64)
+        if proc == Q.BW:
+            a, b = np.where(u <= 0.5, a, 1.0 - a), np.where(u <= 0.5, b, 1.0 - b)
+        ks = _ks_paired(a, b)
         kss.append(ks)
         print(f"  chi={chi:g}: KS(surrogate, table) = {ks:.2e}")
     return kss
+
+
+def _served(s):
+    err, mask = s.bands()
+    served = [(mask >> b) & 1 for b in range(64)]
+    return err, float(np.mean(served))
 
 
 @pytest.mark.parametrize("proc", [Q.QS, Q.BW])
 def test_train_ks_fallback(ctx, tables512, trained, proc):
     table = tables512[0] if proc == Q.BW else tables512[1]
     s, loss = trained[proc]
-    print(f"process {proc}: final weighted loss {loss:.3e}")
+    err, served = _served(s)
+    print(f"process {proc}: final weighted loss {loss:.3e}; network serves {served:.2f} of the bands "
+          f"(band errors {err.min():.2e} .. {err.max():.2e})")
     assert np.isfinite(loss)
     rng = np.random.default_rng(5)
-    kss = _ks_by_chi(s, table, proc, rng)
-    # 40000 steps; measured on MI355X: QS <= 1.8e-3, BW <= 3.4e-3 (paired KS
-    # noise with 2^20 samples ~ 1e-4); the bar leaves room for training-order
-    # effects
-    assert max(kss) < 5e-3
+    # the validated domain meets the KS gate at every chi, wherever the
+    # short training left the network (the table serves the rest)
+    chis = list(CHI_GRID) + list(np.exp(rng.uniform(np.log(1e-3), np.log(1e3), 24)))
+    kss = _ks_by_chi(s, table, proc, rng, chis, n=1 << 20)
+    assert max(kss) <= KS_GATE, max(kss)
     # outside the trained range the surrogate is the table, bit for bit
     chi = np.exp(rng.uniform(np.log(2e3), np.log(9e3), 10000)).astype(np.float32)
     u = rng.random(10000).astype(np.float32)
@@ -160,17 +191,54 @@ def test_train_ks_fallback(ctx, tables512, trained, proc):
     np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
 
 
+@pytest.fixture(scope="module")
+def bench_trained(ctx, tables512):
+    """Both surrogates with the training the benchmark uses: 2^24 samples,
+    half of them even in the network's second input, 320000 Adam steps of
+    16384, band validation at 8e-4."""
+    out = {}
+    for proc in (Q.BW, Q.QS):
+        table = tables512[0] if proc == Q.BW else tables512[1]
+        cfg = Q.Surrogate.cfg(proc, 1e-3, 1e3, n_samples=1 << 24, batch=16384, steps=320000, lr=3e-3,
+                              probe_tol=1.0, tail_permille=500, ks_budget=KS_BUDGET)
+        out[proc] = Q.Surrogate.train(ctx, table, cfg)
+    return out
+
+
 @pytest.mark.parametrize("proc", [Q.QS, Q.BW])
-def test_ks_with_benchmark_training(ctx, tables512, proc):
-    """The training the benchmark uses (2^24 samples, 320000 Adam steps of
-    16384): measured on MI355X, KS <= 1e-3 up to chi = 1e2 and 1.05e-3 (QS)
-    / 1.16e-3 (BW) at the upper end of the trained range."""
+def test_ks_with_benchmark_training(ctx, tables512, bench_trained, proc):
+    """With the benchmark's training, the exact KS distance of the surrogate
+    path's spectrum to the table's is within 1e-3 at 13 chi over the trained
+    range and at 24 random chi, 2^21 samples each, and the network serves
+    most of the range."""
     table = tables512[0] if proc == Q.BW else tables512[1]
-    cfg = Q.Surrogate.cfg(proc, 1e-3, 1e3, n_samples=1 << 24, batch=16384, steps=320000, lr=3e-3, probe_tol=1.0)
-    s, loss = Q.Surrogate.train(ctx, table, cfg)
-    print(f"process {proc}: final weighted loss {loss:.3e}")
-    kss = _ks_by_chi(s, table, proc, np.random.default_rng(6))
-    assert max(kss[:-1]) < 1.2e-3 and kss[-1] < 1.6e-3
+    s, loss = bench_trained[proc]
+    err, served = _served(s)
+    print(f"process {proc}: final weighted loss {loss:.3e}; network serves {served:.2f} of the bands")
+    rng = np.random.default_rng(6)
+    chis = list(CHI_GRID) + list(np.exp(rng.uniform(np.log(1e-3), np.log(1e3), 24)))
+    kss = _ks_by_chi(s, table, proc, rng, chis)
+    assert max(kss) <= KS_GATE, max(kss)
+    assert served >= 0.5
+
+
+def test_band_validation_refuses_an_untrained_network(ctx, tables512):
+    """A network with random weights fails the validation in every band, so
+    the surrogate path samples exactly as the table does."""
+    table = tables512[1]
+    s = Q.Surrogate.from_host(table, Q.Surrogate.cfg(Q.QS, 1e-3, 1e3, ks_budget=KS_BUDGET), _random_params(9))
+    err, served = _served(s)
+    assert served == 0.0 and err.min() > KS_BUDGET
+    rng = np.random.default_rng(10)
+    n = 1 << 16
+    chi = np.exp(rng.uniform(np.log(1e-3), np.log(1e3), n)).astype(np.float32)
+    u = rng.random(n).astype(np.float32)
+    dc, du = torch.as_tensor(chi).cuda(), torch.as_tensor(u).cuda()
+    a, b = torch.empty_like(dc), torch.empty_like(dc)
+    s.sample(dc, du, a)
+    Q.table_sample(table, dc, du, b)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
 
 
 def test_step_with_surrogate_probe_and_counts(ctx, tables):
@@ -227,38 +295,47 @@ def test_step_with_surrogate_probe_and_counts(ctx, tables):
     assert ks < 0.1
 
 
-def test_gain_over_table(ctx, tables512, trained):
-    """What the network buys over the table: sampling time for 2^26 events
-    with chi log-uniform over the trained range plus 2^16 out-of-range
-    events (which fall back to the table), both kernels timed with HIP
-    events on the launch stream, and the memory each needs; the fallback
-    events match the table bit for bit.  The times are reported, not
-    asserted: with 512 x 512 FP32 tables resident in L2 the table search is
-    the faster of the two on this hardware."""
-    n_in, n_out = 1 << 26, 1 << 16
-    for proc in (Q.QS, Q.BW):
-        table = tables512[0] if proc == Q.BW else tables512[1]
-        s, _ = trained[proc]
-        chi = np.concatenate([QI.loguniform_chi(n_in, 3, 1e-3, 1e3), QI.loguniform_chi(n_out, 4, 2e3, 9e3)])
-        u = QI.uniforms(n_in + n_out, 3, stream=proc)
-        dc = torch.as_tensor(chi.astype(np.float32)).cuda()
-        du = torch.as_tensor(u.astype(np.float32)).cuda()
-        a, b = torch.empty_like(dc), torch.empty_like(dc)
-        times = {}
-        for name, fn in (("table", lambda: Q.table_sample(table, dc, du, b)), ("surrogate", lambda: s.sample(dc, du, a))):
+@pytest.mark.parametrize("proc", [Q.QS, Q.BW])
+def test_gain_over_table(ctx, tables512, bench_trained, proc):
+    """What the trained network gains over the table it replaces, and where.
+    The standalone sampling call over 2^24 events (chi log-uniform over the
+    trained range, 2^16 more outside it), timed with HIP events, for the
+    table alone and for the network (its validated bands; the table
+    elsewhere), with tables of 512^2, 2048^2 and 4096^2 points: 2, 32 and
+    128 MiB of FP32 row pairs, the network 26 KB.  With tables resident in
+    the L2 of an XCD (4 MiB) the table search is the faster; once they
+    outgrow it, the search's scattered probes miss and the network gains.
+    Asserted: the network path is faster than the 4096^2 table, and the
+    out-of-range events match the table bit for bit."""
+    n_in, n_out = 1 << 24, 1 << 16
+    params = bench_trained[proc][0].params()
+    chi = np.concatenate([QI.loguniform_chi(n_in, 3, 1e-3, 1e3), QI.loguniform_chi(n_out, 4, 2e3, 9e3)])
+    u = QI.uniforms(n_in + n_out, 3, stream=proc)
+    dc = torch.as_tensor(chi.astype(np.float32)).cuda()
+    du = torch.as_tensor(u.astype(np.float32)).cuda()
+    a, b = torch.empty_like(dc), torch.empty_like(dc)
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
             fn()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(10):
-                fn()
-            e1.record()
-            torch.cuda.synchronize()
-            times[name] = e0.elapsed_time(e1) / 10
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    gains = {}
+    for size in (512, 2048, 4096):
+        table = (tables512[0] if proc == Q.BW else tables512[1]) if size == 512 else \
+            Q.Table.generate_device(proc, RANGE[0], RANGE[1], size, size).to_device()
+        s = Q.Surrogate.from_host(table, Q.Surrogate.cfg(proc, 1e-3, 1e3, ks_budget=KS_BUDGET), params)
+        _, served = _served(s)
+        t_table = timed(lambda: Q.table_sample(table, dc, du, b))
+        t_net = timed(lambda: s.sample(dc, du, a))
         np.testing.assert_array_equal(a[n_in:].cpu().numpy(), b[n_in:].cpu().numpy())
-        tp = table.host_data()[0]
-        print(f"process {proc}: table {times['table']:.3f} ms, surrogate {times['surrogate']:.3f} ms "
-              f"for {n_in + n_out} events, {n_out / (n_in + n_out):.2e} of them out of range "
-              f"(gain x{times['table'] / times['surrogate']:.2f}); "
-              f"table {4 * tp.n_chi * (tp.n_frac + 1)} B in FP32, network {4 * 4417 + 2 * 4096} B")
-        assert times["surrogate"] > 0 and times["table"] > 0
+        gains[size] = t_table / t_net
+        print(f"process {proc}, {size}^2 tables ({4 * (size - 1) * size * 2 / 2**20:.1f} MiB FP32): table "
+              f"{t_table:.3f} ms, network {t_net:.3f} ms (serving {served:.2f} of the bands), gain x{gains[size]:.2f}")
+    assert gains[4096] > 1.0, gains
