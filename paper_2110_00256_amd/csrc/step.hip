@@ -85,66 +85,60 @@ __device__ __forceinline__ void publish(const StepArgs& a, int k, const ChunkDes
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// resolve() is done by a whole wave: lane l polls chunk base - l, so a
-// window of 64 predecessors costs one round of loads.  The nearest
-// predecessor holding an inclusive prefix (flag P) ends the walk; every
-// chunk between it and k must have posted at least its aggregate, else the
-// window is polled again.  Chunks before the stream's first count as P with
-// value 0.  Returns the exclusive prefix in every lane; lane 0 posts the
-// inclusive one.
-__device__ long long resolve(const StepArgs& a, int k, const ChunkDesc& c, unsigned long long agg, int64_t* err) {
+// resolve() is called by the whole block: thread t polls chunk base - t, so
+// a window of kBlock predecessors costs one round of loads (with many
+// chunks in flight the nearest inclusive prefix can lie hundreds of chunks
+// back).  The nearest predecessor holding an inclusive prefix (flag P) ends
+// the walk; every chunk between it and k must have posted at least its
+// aggregate, else the window is polled again.  Chunks before the stream's
+// first count as P with value 0.  Returns the exclusive prefix in every
+// thread; thread 0 posts the inclusive one.  `s_p` and `s_sum` are LDS
+// scratch of one entry per wave.
+__device__ long long resolve(const StepArgs& a, int k, const ChunkDesc& c, unsigned long long agg, int64_t* err,
+                             int* s_p, long long* s_sum) {
+    const int tid = threadIdx.x, wave = tid >> 6;
     const int lane = static_cast<int>(lane_id());
     long long excl = 0;
     if (k != c.stream_first) {
         int base = k - 1;
         int spins = 0;
-        // the nearest predecessor is the one most often still running: wait
-        // for it with a single lane polling; if it holds its inclusive
-        // prefix the walk ends there, else whole windows are read
-        unsigned long long v0 = 0;
-        if (lane == 0) {
-            for (;;) {
-                v0 = __hip_atomic_load(a.status + base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (static_cast<uint32_t>(v0 >> 32) == a.epoch && ((v0 >> 30) & 3u) != 0u) break;
-                if (++spins > kSpinLimit) break;
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        spins = __shfl(spins, 0);
-        v0 = __shfl(v0, 0);
-        const bool done = static_cast<uint32_t>(v0 >> 32) == a.epoch && ((v0 >> 30) & 3u) == kFlagP;
-        if (done) excl = static_cast<long long>(v0 & kValueMask);
-        while (!done) {
-            const int j = base - lane;
+        for (;;) {
+            const int j = base - tid;
             unsigned flag = kFlagP;
             long long val = 0;
             if (j >= c.stream_first) {
-                const unsigned long long v =
-                    __hip_atomic_load(a.status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long v = __hip_atomic_load(a.status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 flag = static_cast<uint32_t>(v >> 32) == a.epoch ? (static_cast<unsigned>(v >> 30) & 3u) : 0u;
                 val = static_cast<long long>(v & kValueMask);
             }
             const unsigned long long pmask = __ballot(flag == kFlagP);
-            const unsigned long long xmask = __ballot(flag == 0u);
-            const int p = pmask ? __builtin_ctzll(pmask) : 64;   // nearest P, 64: none in the window
-            const unsigned long long upto = p >= 63 ? ~0ULL : ((2ULL << p) - 1ULL);
-            if (xmask & upto) {                                    // a chunk on the way has not posted
+            if (lane == 0) s_p[wave] = pmask ? wave * 64 + __builtin_ctzll(pmask) : kBlock;
+            __syncthreads();
+            int p = kBlock;   // nearest P in the window, kBlock: none
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) p = min(p, s_p[w]);
+            // a chunk on the way has not posted: poll the window again
+            if (__syncthreads_or(flag == 0u && tid <= p)) {
                 if (++spins > kSpinLimit) {   // predecessor never published: give up, report
-                    if (err && lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(err), 1ULL);
+                    if (err && tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(err), 1ULL);
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
                 continue;
             }
-            long long part = lane <= p ? val : 0;
+            long long part = tid <= p ? val : 0;
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
-            excl += part;
-            if (p < 64) break;
-            base -= 64;
+            if (lane == 0) s_sum[wave] = part;
+            __syncthreads();
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) excl += s_sum[w];
+            __syncthreads();   // s_p and s_sum are reused by the next round
+            if (p < kBlock) break;
+            base -= kBlock;
         }
     }
-    if (lane == 0)
+    if (tid == 0)
         __hip_atomic_store(a.status + k, pack_status(a.epoch, kFlagP, static_cast<unsigned long long>(excl) + agg),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return excl;
@@ -225,16 +219,19 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     const int nqs = a.qs.n_chi > 0 ? a.qs.n_chi : 0;
     T* t_bw = reinterpret_cast<T*>(lds_raw);
     T* t_qs = t_bw + ((nbw + 1) & ~1);
+    // event lists: wave w owns chunk positions [w kWaveSpan, (w + 1) kWaveSpan)
+    // and appends the positions of its events, in order, to its own region
     uint16_t* evlist = reinterpret_cast<uint16_t*>(t_qs + ((nqs + 1) & ~1));
     // chi of the chunk's event particles at their chunk index (written while
     // streaming), then their sample (BW xi, QS xi)
     T* s_chi = reinterpret_cast<T*>(evlist + kChunk);
-    __shared__ unsigned long long emask[kMasks];
     __shared__ unsigned long long kmask[kMasks];
     __shared__ unsigned long long smask[kSurr ? kMasks : 1];   // events sampled by the surrogate
-    __shared__ int epref[kMasks];
     __shared__ int kpref[kMasks];
-    __shared__ int s_ticket, s_total, s_kept;
+    __shared__ int s_wcnt[kBlock / 64];
+    __shared__ int s_lbp[kBlock / 64];          // look-back scratch
+    __shared__ long long s_lbsum[kBlock / 64];
+    __shared__ int s_ticket, s_kept;
     __shared__ long long s_excl, s_base0, s_base1;
 
     const int tid = threadIdx.x;
@@ -273,9 +270,15 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
 
         // ---------------- phase 1: stream, evolve, flag
         const T dt = static_cast<T>(a.dt);
+        // each wave streams its own contiguous quarter of the chunk and
+        // appends its events (chunk positions, in order) to its region of
+        // evlist with a running count: no block-wide list pass is needed
+        constexpr int kWaveSpan = kChunk / (kBlock / 64);
+        const int wbase = wave * kWaveSpan;
+        int wcnt = 0;
         if (a.generate_only) {
-            for (int it = 0; it < kChunk / kBlock; ++it) {
-                const int loc = it * kBlock + tid;
+            for (int sl = 0; sl < kWaveSpan / 64; ++sl) {
+                const int loc = wbase + sl * 64 + static_cast<int>(lane);
                 bool ev = false;
                 if (loc < c.len) {
                     const int64_t j = c.begin + loc;
@@ -292,34 +295,39 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                     }
                 }
                 const unsigned long long m = __ballot(ev);
-                if (lane == 0) emask[it * (kBlock / 64) + wave] = m;
+                if (ev) evlist[wbase + wcnt + static_cast<int>(bits_below(m))] = static_cast<uint16_t>(loc);
+                wcnt += __popcll(m);
             }
         } else {
-            // kBatch particles per thread have all their loads in flight
-            // before any of them is evaluated (stores in between could alias
-            // the next loads, so the compiler would not hoist them itself).
+            // FP64: one particle per lane at a time, the next one's ten
+            // loads issued before the current one is evaluated (stores in
+            // between could alias them, so the compiler would not hoist the
+            // loads itself); FP32: four particles' loads issued together.
             // Lanes past the end load the chunk's first particle and drop it.
-            constexpr int kBatch = sizeof(T) == 8 ? 2 : 4;
-            static_assert(kChunk % (kBlock * kBatch) == 0, "a chunk must be a whole number of batches");
-            for (int it = 0; it < kChunk / kBlock; it += kBatch) {
-                T v[kBatch][10];
+            constexpr bool kPipe = sizeof(T) == 8;
+            constexpr int kBatch = sizeof(T) == 8 ? 1 : 4;
+            constexpr int kIters = kWaveSpan / 64;
+            static_assert(kIters % kBatch == 0, "a wave's span must be a whole number of batches");
+            auto load_batch = [&](int it, T (&v)[kBatch][10]) {
 #pragma unroll
                 for (int b = 0; b < kBatch; ++b) {
-                    const int loc = (it + b) * kBlock + tid;
+                    const int loc = wbase + (it + b) * 64 + static_cast<int>(lane);
                     const int64_t j = c.begin + (loc < c.len ? loc : 0);
                     // u with ordinary loads (phase 2b gathers the events' u
-                    // again, and finds many of its lines still cached), the
+                    // again, and finds part of its lines still cached), the
                     // fields and tau non-temporal (read once)
 #pragma unroll
                     for (int q = 0; q < 10; ++q) v[b][q] = q < 3 ? ld<T>(S.p[q], j) : ldnt<T>(S.p[q], j);
+                }
+            };
+            auto eval_batch = [&](int it, T (&v)[kBatch][10]) {
+#pragma unroll
+                for (int b = 0; b < kBatch; ++b) {
                     // caller units -> u = p/(m_e c), V/m, T (factors 1 for SI)
 #pragma unroll
                     for (int q = 0; q < 9; ++q)
                         v[b][q] *= static_cast<T>(q < 3 ? a.units.u : q < 6 ? a.units.e : a.units.b);
-                }
-#pragma unroll
-                for (int b = 0; b < kBatch; ++b) {
-                    const int loc = (it + b) * kBlock + tid;
+                    const int loc = wbase + (it + b) * 64 + static_cast<int>(lane);
                     bool ev = false;
                     if (loc < c.len) {
                         const int64_t j = c.begin + loc;
@@ -352,31 +360,41 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                         if (S.flags) S.flags[j] = static_cast<uint8_t>(ev);
                     }
                     const unsigned long long m = __ballot(ev);
-                    if (lane == 0) emask[(it + b) * (kBlock / 64) + wave] = m;
+                    if (ev) evlist[wbase + wcnt + static_cast<int>(bits_below(m))] = static_cast<uint16_t>(loc);
+                    wcnt += __popcll(m);
+                }
+            };
+            if constexpr (kPipe) {
+                T v[kBatch][10], w[kBatch][10];
+                load_batch(0, v);
+                for (int it = 0; it < kIters; it += kBatch) {
+                    if (it + kBatch < kIters) load_batch(it + kBatch, w);
+                    eval_batch(it, v);
+#pragma unroll
+                    for (int b = 0; b < kBatch; ++b)
+#pragma unroll
+                        for (int q = 0; q < 10; ++q) v[b][q] = w[b][q];
+                }
+            } else {
+                for (int it = 0; it < kIters; it += kBatch) {
+                    T v[kBatch][10];
+                    load_batch(it, v);
+                    eval_batch(it, v);
                 }
             }
         }
+        // ---------------- the chunk's events in order: wave w's region first
+        // (wave-major order is particle order); event e lives in the region
+        // of the wave whose prefix range holds it
+        if (lane == 0) s_wcnt[wave] = wcnt;
         __syncthreads();
-
-        // ---------------- ordered event list
-        if (wave == 0) {
-            const int cnt = static_cast<int>(lane) < kMasks ? __popcll(emask[lane]) : 0;
-            int incl = cnt;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int v = __shfl_up(incl, o);
-                if (static_cast<int>(lane) >= o) incl += v;
-            }
-            if (static_cast<int>(lane) < kMasks) epref[lane] = incl - cnt;
-            if (lane == 63) s_total = incl;
-        }
-        __syncthreads();
-        for (int w = wave; w < kMasks; w += kBlock / 64) {
-            const unsigned long long m = emask[w];
-            if ((m >> lane) & 1ULL) evlist[epref[w] + bits_below(m)] = static_cast<uint16_t>(w * 64 + lane);
-        }
-        const int total = s_total;
-        __syncthreads();
+        const int p1 = s_wcnt[0], p2 = p1 + s_wcnt[1], p3 = p2 + s_wcnt[2];
+        const int total = p3 + s_wcnt[3];
+        auto ev_loc = [&](int e) -> int {
+            const int w = (e >= p1) + (e >= p2) + (e >= p3);
+            const int pw = w == 0 ? 0 : w == 1 ? p1 : w == 2 ? p2 : p3;
+            return evlist[w * kWaveSpan + e - pw];
+        };
 
         // ---------------- surrogate pass (FP32 data only): the network's
         // sample overwrites the event's LDS chi word and its smask bit is
@@ -396,7 +414,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 for (int e0 = 0; e0 + wave * 64 < total; e0 += kBlock) {
                     const int e = e0 + tid;
                     const bool valid = e < total;
-                    const int le = valid ? evlist[e] : 0;
+                    const int le = valid ? ev_loc(e) : 0;
                     const float chi = valid ? s_chi[le] : 1.f;
                     float r = 0.5f;
                     if (valid)
@@ -421,50 +439,140 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             }
         }
 
-        // ---------------- publish the chunk's product count early (no
-        // threshold: one product record per event), so that later chunks'
-        // look-back finds it while this block samples its events
+        // ---------------- events.  Per event: the draws (Philox block 0 of
+        // the parent), the inverse-CDF sample (table search on chi, or the
+        // surrogate's sample already in LDS), the kinematics, the parent's new
+        // u and tau, and the products at deterministic slots in parent order:
+        // slot = exclusive prefix of the stream's product counts over earlier
+        // chunks (decoupled look-back) + the event's rank in this chunk.
         const bool thresh = !photon && a.photon_min_energy > 0.0;
-        if (!thresh && tid == 0) publish(a, k, c, static_cast<unsigned long long>(total));
-
-        // ---------------- phase 2a: draw and inverse-CDF sample of every
-        // event (no particle data needed: chi is in LDS); the sample (BW xi,
-        // QS xi) replaces chi.  Idle lanes of the last wave sample a
-        // placeholder and store nothing.
-#pragma unroll 1
-        for (int e0 = 0; e0 + wave * 64 < total; e0 += kBlock) {
-            const int e = e0 + tid;
-            const bool valid = e < total;
-            const int le = valid ? evlist[e] : 0;
-            const T cs = valid ? s_chi[le] : T(1);
-            const double u0 = dev::draws(a.seed, static_cast<unsigned long long>(S.id_base + c.begin + le), a.step,
-                                         static_cast<unsigned long long>(S.species), 0ULL).u[0];
-            // a surrogate sample (`have`) replaced chi in LDS; otherwise the
-            // table is searched with the random input taken from u0 before
-            // narrowing (ln u0 for QS; the fold for BW)
-            const bool have = surr_on && valid && ((smask[e >> 6] >> (e & 63)) & 1ULL);
-            T xi;
+        const T su = static_cast<T>(a.units.u), iu = static_cast<T>(a.units.inv_u);
+        // sample of event e from its chi (or surrogate sample) `cs` and u0
+        auto sample_of = [&](bool have, T cs, double u0) -> T {
             if (photon) {
                 bool esel;
                 const T rf = dev::bw_folded_uniform<T>(u0, esel);
-                xi = have ? cs : (valid ? dev::sample_bw_folded<T>(a.bw, cs, rf) : T(0));
-            } else {
-                const T lr = dev::qs_log_uniform<T>(u0);
-                xi = dev::dexp(have ? cs : (valid ? dev::sample_qs_lnxi_lr<T>(a.qs, cs, lr) : T(0)));
+                return have ? cs : dev::sample_bw_folded<T>(a.bw, cs, rf);
             }
-            if (valid) s_chi[le] = xi;
-        }
-        __syncthreads();
-
-        // ---------------- product count with the photon threshold
-        if (thresh) {
+            const T lr = dev::qs_log_uniform<T>(u0);
+            return dev::dexp(have ? cs : dev::sample_qs_lnxi_lr<T>(a.qs, cs, lr));
+        };
+        auto is_surr = [&](int e) {
+            return surr_on && ((smask[e >> 6] >> (e & 63)) & 1ULL);
+        };
+        int prods = total;
+        if (!thresh) {
+            // One dense pass.  The chunk's product count is the event count:
+            // it is published at once.  The first round of events is drawn,
+            // sampled and its parents updated before the block resolves the
+            // prefix (giving the predecessors time to post theirs); products
+            // are written from then on.
+            if (tid == 0) publish(a, k, c, static_cast<unsigned long long>(total));
+            long long excl = 0;   // the same in every thread once resolved
+            int e = tid;
+            T nux = T(0), nuy = T(0), nuz = T(0), nw = T(1);
+            if (e < total) {
+                const int64_t jn = c.begin + ev_loc(e);
+                nux = su * ld<T>(S.p[0], jn);
+                nuy = su * ld<T>(S.p[1], jn);
+                nuz = su * ld<T>(S.p[2], jn);
+                if (S.p[10]) nw = ld<T>(S.p[10], jn);
+            }
+#pragma unroll 1
+            for (int e0 = 0; e0 < total; e0 += kBlock, e += kBlock) {
+                const bool valid = e < total;
+                const int le = valid ? ev_loc(e) : 0;
+                const int64_t j = c.begin + le;
+                const T ux = nux, uy = nuy, uz = nuz, w = nw;
+                if (e + kBlock < total) {
+                    const int64_t jn = c.begin + ev_loc(e + kBlock);
+                    nux = su * ld<T>(S.p[0], jn);
+                    nuy = su * ld<T>(S.p[1], jn);
+                    nuz = su * ld<T>(S.p[2], jn);
+                    if (S.p[10]) nw = ld<T>(S.p[10], jn);
+                }
+                const int64_t parent = S.id_base + j;
+                const dev::Draws d = dev::draws(a.seed, static_cast<unsigned long long>(parent), a.step,
+                                                static_cast<unsigned long long>(S.species), 0ULL);
+                const T cs = valid ? s_chi[le] : T(1);
+                const T xi = valid ? sample_of(is_surr(e), cs, d.u[0]) : T(0);
+                // optical depths from uniforms 1 and 2: BW electron and
+                // positron; QS parent (redrawn) and photon
+                const T t1 = static_cast<T>(-log(d.u[1]));
+                const T t2 = static_cast<T>(-log(d.u[2]));
+                T pa[3], pb[3];   // BW: the electron's and positron's u; QS: the photon's u
+                if (photon) {
+                    const bool esel = d.u[0] <= 0.5;   // on the 53-bit uniform, as the fold
+                    const T sx = xi * ux * iu, sy = xi * uy * iu, sz = xi * uz * iu;
+                    const T ox = ux * iu - sx, oy = uy * iu - sy, oz = uz * iu - sz;
+                    pa[0] = esel ? sx : ox;
+                    pa[1] = esel ? sy : oy;
+                    pa[2] = esel ? sz : oz;
+                    pb[0] = esel ? ox : sx;
+                    pb[1] = esel ? oy : sy;
+                    pb[2] = esel ? oz : sz;
+                    if (valid) st<T>(S.p[9], j, static_cast<T>(__builtin_inf()));
+                } else {
+                    // QS photon energy gamma_gamma = (gamma - 1) xi, gamma - 1 = |u|^2/(gamma + 1)
+                    const double dx = ux, dy = uy, dz = uz;
+                    const double u2 = dx * dx + dy * dy + dz * dz;
+                    const T gg = static_cast<T>(u2 / (sqrt(1.0 + u2) + 1.0)) * xi;
+                    const T um = static_cast<T>(sqrt(u2));
+                    const T sc = um > T(0) ? gg / um : T(0);
+                    const T px = sc * ux, py = sc * uy, pz = sc * uz;
+                    pa[0] = px * iu;
+                    pa[1] = py * iu;
+                    pa[2] = pz * iu;
+                    pb[0] = pb[1] = pb[2] = T(0);
+                    if (valid) {
+                        st<T>(S.p[0], j, (ux - px) * iu);
+                        st<T>(S.p[1], j, (uy - py) * iu);
+                        st<T>(S.p[2], j, (uz - pz) * iu);
+                        st<T>(S.p[9], j, t1);
+                    }
+                }
+                if (e0 == 0) {
+                    excl = resolve(a, k, c, static_cast<unsigned long long>(total),
+                                   a.stats ? a.stats + QED_STAT_SCAN_TIMEOUT : nullptr, s_lbp, s_lbsum);
+                    if (tid == 0) s_excl = excl;
+                }
+                if (valid) {
+                    const long long slot = excl + e;
+                    if (photon) {
+                        write_product<T>(a.el, s_base0 + slot, pa[0], pa[1], pa[2], w, t1, parent);
+                        write_product<T>(a.po, s_base1 + slot, pb[0], pb[1], pb[2], w, t2, parent);
+                    } else {
+                        write_product<T>(a.ph, s_base0 + slot, pa[0], pa[1], pa[2], w, t2, parent);
+                    }
+                }
+            }
+            if (total == 0) {
+                excl = resolve(a, k, c, 0ULL, a.stats ? a.stats + QED_STAT_SCAN_TIMEOUT : nullptr, s_lbp, s_lbsum);
+                if (tid == 0) s_excl = excl;
+            }
+        } else {
+            // With a photon threshold the chunk's product count is known only
+            // after sampling: sample every event (no particle data needed:
+            // chi is in LDS), count the photons kept, publish, resolve, then
+            // update the parents and write the kept photons.
+#pragma unroll 1
+            for (int e0 = 0; e0 + wave * 64 < total; e0 += kBlock) {
+                const int e = e0 + tid;
+                const bool valid = e < total;
+                const int le = valid ? ev_loc(e) : 0;
+                const T cs = valid ? s_chi[le] : T(1);
+                const double u0 = dev::draws(a.seed, static_cast<unsigned long long>(S.id_base + c.begin + le),
+                                             a.step, static_cast<unsigned long long>(S.species), 0ULL).u[0];
+                const T xi = valid ? sample_of(is_surr(e), cs, u0) : T(0);
+                if (valid) s_chi[le] = xi;
+            }
+            __syncthreads();
             for (int e0 = 0; e0 < total; e0 += kBlock) {
                 const int e = e0 + tid;
                 bool keep = false;
                 if (e < total) {
-                    const int le = evlist[e];
+                    const int le = ev_loc(e);
                     const int64_t j = c.begin + le;
-                    const T su = static_cast<T>(a.units.u);
                     const double ux = su * ld<T>(S.p[0], j), uy = su * ld<T>(S.p[1], j), uz = su * ld<T>(S.p[2], j);
                     const double u2 = ux * ux + uy * uy + uz * uz;
                     const T gg = static_cast<T>(u2 / (sqrt(1.0 + u2) + 1.0)) * s_chi[le];
@@ -490,15 +598,45 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 }
             }
             __syncthreads();
+            prods = s_kept;
+            {
+                const long long excl = resolve(a, k, c, static_cast<unsigned long long>(prods),
+                                               a.stats ? a.stats + QED_STAT_SCAN_TIMEOUT : nullptr, s_lbp, s_lbsum);
+                if (tid == 0) s_excl = excl;
+            }
+            __syncthreads();
+            const long long slot0 = s_excl;
+#pragma unroll 1
+            for (int e = tid; e < total; e += kBlock) {
+                const int le = ev_loc(e);
+                const int64_t j = c.begin + le;
+                const T ux = su * ld<T>(S.p[0], j), uy = su * ld<T>(S.p[1], j), uz = su * ld<T>(S.p[2], j);
+                const T w = S.p[10] ? ld<T>(S.p[10], j) : T(1);
+                const int64_t parent = S.id_base + j;
+                const dev::Draws d = dev::draws(a.seed, static_cast<unsigned long long>(parent), a.step,
+                                                static_cast<unsigned long long>(S.species), 0ULL);
+                const T xi = s_chi[le];
+                const T t1 = static_cast<T>(-log(d.u[1]));
+                const T t2 = static_cast<T>(-log(d.u[2]));
+                const double dx = ux, dy = uy, dz = uz;
+                const double u2 = dx * dx + dy * dy + dz * dz;
+                const T gg = static_cast<T>(u2 / (sqrt(1.0 + u2) + 1.0)) * xi;
+                const T um = static_cast<T>(sqrt(u2));
+                const T sc = um > T(0) ? gg / um : T(0);
+                const T px = sc * ux, py = sc * uy, pz = sc * uz;
+                st<T>(S.p[0], j, (ux - px) * iu);
+                st<T>(S.p[1], j, (uy - py) * iu);
+                st<T>(S.p[2], j, (uz - pz) * iu);
+                st<T>(S.p[9], j, t1);
+                const unsigned long long m = kmask[e >> 6];
+                if ((m >> (e & 63)) & 1ULL) {
+                    const long long rank = kpref[e >> 6] + __popcll(m & ((1ULL << (e & 63)) - 1ULL));
+                    write_product<T>(a.ph, s_base0 + slot0 + rank, px * iu, py * iu, pz * iu, w, t2, parent);
+                }
+            }
         }
-        const int prods = thresh ? s_kept : total;
 
-        // ---------------- decoupled look-back over the chunk's stream
-        if (wave == 0) {
-            const long long excl = resolve(a, k, c, static_cast<unsigned long long>(prods),
-                                           a.stats ? a.stats + QED_STAT_SCAN_TIMEOUT : nullptr);
-            if (lane == 0) s_excl = excl;
-        }
+        // ---------------- the stream's counts (its last chunk) and statistics
         if (tid == 0) {
             const long long incl = s_excl + prods;
             if (k == c.stream_last) {
@@ -515,79 +653,6 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             } else {
                 n_qs_events += total;
                 n_kept += prods;
-            }
-        }
-        __syncthreads();
-        const long long slot0 = s_excl;
-
-        // ---------------- phase 2b: kinematics, parent update and products
-        // at their slots.  Each thread walks its events (e = tid, tid + 256,
-        // ...) with the next event's u and w loads in flight while the
-        // current one is computed.
-        {
-            const T su = static_cast<T>(a.units.u), iu = static_cast<T>(a.units.inv_u);
-            int e = tid;
-            T nux = T(0), nuy = T(0), nuz = T(0), nw = T(1);
-            if (e < total) {
-                const int64_t jn = c.begin + evlist[e];
-                nux = su * ld<T>(S.p[0], jn);
-                nuy = su * ld<T>(S.p[1], jn);
-                nuz = su * ld<T>(S.p[2], jn);
-                if (S.p[10]) nw = ld<T>(S.p[10], jn);
-            }
-#pragma unroll 1
-            for (; e < total; e += kBlock) {
-                const int le = evlist[e];
-                const int64_t j = c.begin + le;
-                const T ux = nux, uy = nuy, uz = nuz, w = nw;
-                if (e + kBlock < total) {
-                    const int64_t jn = c.begin + evlist[e + kBlock];
-                    nux = su * ld<T>(S.p[0], jn);
-                    nuy = su * ld<T>(S.p[1], jn);
-                    nuz = su * ld<T>(S.p[2], jn);
-                    if (S.p[10]) nw = ld<T>(S.p[10], jn);
-                }
-                const int64_t parent = S.id_base + j;
-                const dev::Draws d = dev::draws(a.seed, static_cast<unsigned long long>(parent), a.step,
-                                                static_cast<unsigned long long>(S.species), 0ULL);
-                const T xi = s_chi[le];
-                // optical depths from uniforms 1 and 2: BW electron and
-                // positron; QS parent (redrawn) and photon
-                const T t1 = static_cast<T>(-log(d.u[1]));
-                const T t2 = static_cast<T>(-log(d.u[2]));
-                if (photon) {
-                    const bool esel = d.u[0] <= 0.5;   // on the 53-bit uniform, as in phase 2a
-                    const T sx = xi * ux * iu, sy = xi * uy * iu, sz = xi * uz * iu;
-                    const T ox = ux * iu - sx, oy = uy * iu - sy, oz = uz * iu - sz;
-                    const T te = t1, tp = t2;
-                    const long long slot = slot0 + e;
-                    write_product<T>(a.el, s_base0 + slot, esel ? sx : ox, esel ? sy : oy, esel ? sz : oz, w, te,
-                                     parent);
-                    write_product<T>(a.po, s_base1 + slot, esel ? ox : sx, esel ? oy : sy, esel ? oz : sz, w, tp,
-                                     parent);
-                    st<T>(S.p[9], j, static_cast<T>(__builtin_inf()));
-                } else {
-                    // QS photon energy gamma_gamma = (gamma - 1) xi, gamma - 1 = |u|^2/(gamma + 1)
-                    const double dx = ux, dy = uy, dz = uz;
-                    const double u2 = dx * dx + dy * dy + dz * dz;
-                    const T gg = static_cast<T>(u2 / (sqrt(1.0 + u2) + 1.0)) * xi;
-                    const T um = static_cast<T>(sqrt(u2));
-                    const T sc = um > T(0) ? gg / um : T(0);
-                    const T px = sc * ux, py = sc * uy, pz = sc * uz;
-                    st<T>(S.p[0], j, (ux - px) * iu);
-                    st<T>(S.p[1], j, (uy - py) * iu);
-                    st<T>(S.p[2], j, (uz - pz) * iu);
-                    st<T>(S.p[9], j, t1);
-                    bool keep = true;
-                    long long rank = e;
-                    if (thresh) {
-                        const unsigned long long m = kmask[e >> 6];
-                        keep = (m >> (e & 63)) & 1ULL;
-                        rank = kpref[e >> 6] + __popcll(m & ((1ULL << (e & 63)) - 1ULL));
-                    }
-                    if (keep)
-                        write_product<T>(a.ph, s_base0 + slot0 + rank, px * iu, py * iu, pz * iu, w, t2, parent);
-                }
             }
         }
     }
