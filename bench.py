@@ -39,10 +39,17 @@ BYTES = {
     "f64": dict(base=88, qs_event=80, bw_event=104),
     "f32": dict(base=44, qs_event=44, bw_event=60),
 }
+# the same split into bytes read and written: per update u, E, B, tau read and
+# tau written; per QS event w read, parent u, photon (u, w, tau) and parent id
+# written; per BW event w read, two products and their parent ids written
+BYTES_RW = {
+    "f64": dict(base=(80, 8), qs_event=(8, 72), bw_event=(8, 96)),
+    "f32": dict(base=(40, 4), qs_event=(4, 40), bw_event=(4, 56)),
+}
 
 
 # HBM bytes per launch measured with rocprofv3 (FETCH_SIZE, WRITE_SIZE, each
-# calibrated on a plain copy) live in this summary, tagged with a digest of
+# calibrated on a stream with the step's own access pattern) live in this summary, tagged with a digest of
 # the step kernel's sources; they are reported only while the digest matches.
 PROFILE = os.path.join(ROOT, "profiles", "step_kernel_cone_2x2e24.md")
 KERNEL_SOURCES = ("step.hip", "device_physics.hpp", "internal.hpp", "surrogate.hpp", "constants.hpp")
@@ -57,13 +64,15 @@ def kernel_digest():
 
 
 def measured_traffic():
-    """{path: HBM bytes per launch} from the profile summary, or {} if stale."""
+    """The profile summary's traffic record ({"bytes_per_launch": {path: HBM
+    bytes}, "fetch_bytes_per_launch", "write_bytes_per_launch",
+    "calibration"}), or {} if the step kernel's sources have changed since."""
     try:
         with open(PROFILE) as f:
             for line in f:
                 if line.startswith("traffic-json: "):
                     d = json.loads(line[len("traffic-json: "):])
-                    return d["bytes_per_launch"] if d.get("source_digest") == kernel_digest() else {}
+                    return d if d.get("source_digest") == kernel_digest() else {}
     except OSError:
         pass
     return {}
@@ -137,6 +146,8 @@ def run_path(Q, torch, ctx, tables, pops, dtype, steps, warmup, dt, chi_mode, se
     qs_ev, bw_ev = int(st[Q.STAT_QS_EVENTS]), int(st[Q.STAT_BW_EVENTS])
     by = BYTES[dtype]
     alg_bytes = by["base"] * updates + by["qs_event"] * qs_ev + by["bw_event"] * bw_ev
+    rw = BYTES_RW[dtype]
+    alg_rw = [rw["base"][i] * updates + rw["qs_event"][i] * qs_ev + rw["bw_event"][i] * bw_ev for i in (0, 1)]
     kern_s = kern_ms.sum() / 1e3
     res = dict(
         updates_per_s=updates / wall,
@@ -145,6 +156,8 @@ def run_path(Q, torch, ctx, tables, pops, dtype, steps, warmup, dt, chi_mode, se
         kernel_ms_median=float(np.median(kern_ms)),
         achieved_gbs=alg_bytes / kern_s / 1e9,
         alg_bytes_per_launch=alg_bytes / steps,
+        alg_read_bytes_per_launch=alg_rw[0] / steps,
+        alg_write_bytes_per_launch=alg_rw[1] / steps,
         qs_event_fraction=qs_ev / (steps * n_e),
         bw_event_fraction=bw_ev / (steps * n_g),
         surrogate_batches=int(st[Q.STAT_SURR_BATCHES]),
@@ -454,8 +467,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2n", type=int, default=22,
                     help="the oracle is timed on the first 2^k particles of each species, whole steps, >= 10 s")
-    ap.add_argument("--copy-calibration-mib", type=int, default=0,
-                    help="run one plain device copy of this size first (HBM counter calibration)")
+    ap.add_argument("--calibration-mib", type=int, default=0,
+                    help="first stream this many MiB with the step's access patterns: non-temporal read, write "
+                         "and copy passes, then temporal read and write passes (qed_traffic_calibrate modes 0-4), "
+                         "so that HBM counters can be scaled for each")
     ap.add_argument("--workload", choices=("cone", "fullstep", "paper", "extras"), default="cone",
                     help="cone: the default roofline workload; fullstep: 4 species in lognormal tiles, "
                          "Gaussian pulse, FP32 table and FP32+surrogate paths; paper: the paper's own "
@@ -471,13 +486,15 @@ def main():
     import paper_2110_00256_amd as Q
     import qed_inputs as QI
 
-    if args.copy_calibration_mib:
-        src = torch.ones(args.copy_calibration_mib << 18, dtype=torch.float32, device="cuda")
+    if args.calibration_mib:
+        nb = args.calibration_mib << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"bench: calibration copy of {args.copy_calibration_mib} MiB done")
+        for mode in (0, 1, 2, 3, 4):
+            Q.traffic_calibrate(src, dst, nb, mode)
+            torch.cuda.synchronize()
+        log(f"bench: calibration passes of {args.calibration_mib} MiB done")
         del src, dst
 
     if args.workload == "fullstep":
@@ -537,8 +554,9 @@ def main():
     # the profile was taken on the default workload (2^24 + 2^24, dt 1e-16 s)
     traffic = measured_traffic() if (args.log2n == 24 and args.dt == 1e-16) else {}
 
-    def traffic_gbs(key, r):
-        return traffic[key] / (r["kernel_ms_mean"] * 1e-3) / 1e9 if key in traffic else None
+    def traffic_gbs(key, r, kind="bytes_per_launch"):
+        v = traffic.get(kind, {}).get(key)
+        return v / (r["kernel_ms_mean"] * 1e-3) / 1e9 if v is not None else None
 
     out = {
         "metric": METRIC,
@@ -561,7 +579,12 @@ def main():
                      "frac": r64["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic_gbs("f64", r64),
                      "kernel": "step_kernel<double>", "kernel_ms_mean": r64["kernel_ms_mean"],
                      "alg_bytes_per_launch": r64["alg_bytes_per_launch"],
-                     "hbm_bytes_per_launch": traffic.get("f64"), "kernel_digest": kernel_digest()},
+                     "hbm_bytes_per_launch": traffic.get("bytes_per_launch", {}).get("f64"),
+                     "traffic_fetch": traffic_gbs("f64", r64, "fetch_bytes_per_launch"),
+                     "traffic_write": traffic_gbs("f64", r64, "write_bytes_per_launch"),
+                     "alg_read_bytes_per_launch": r64["alg_read_bytes_per_launch"],
+                     "alg_write_bytes_per_launch": r64["alg_write_bytes_per_launch"],
+                     "traffic_calibration": traffic.get("calibration"), "kernel_digest": kernel_digest()},
         "cpu_baseline": cpu,
         "cpu_baseline_one_thread": cpu1,
     }

@@ -337,6 +337,15 @@ int32_t qed_step(qed_context* ctx, const qed_step_desc* desc, void* stream);
  * launch per 160 tiles) and rebuilds the chunk table on the device. */
 int32_t qed_step_noalloc(const qed_context* ctx, const qed_step_desc* desc, void* stream);
 
+/* Measurement aid (not part of the method): stream n_bytes (a multiple of
+ * 8) of device memory with the fused step's streaming access pattern,
+ * non-temporal 8-byte loads and stores in a grid-stride loop.  mode 0 reads
+ * src (dst must be a valid device pointer, written only if the data hold a
+ * NaN), 1 writes dst, 2 copies src to dst; modes 3 and 4 read and write like
+ * 0 and 1 with ordinary (temporal) loads and stores.  Used to scale the hardware's
+ * fetch and write counters by what they report for a known byte count. */
+int32_t qed_traffic_calibrate(const void* src, void* dst, int64_t n_bytes, int32_t mode, void* stream);
+
 /* Synchronise `stream` and read an append buffer's count to the host;
  * returns QED_ERR_CAPACITY if it exceeds the buffer's capacity. */
 int32_t qed_read_count(const qed_append* a, int64_t* host_count, void* stream);

@@ -34,7 +34,7 @@ EXPORTS = (
     "qed_table_rate", "qed_table_sample",
     "qed_surrogate_train", "qed_surrogate_from_host", "qed_surrogate_get_params", "qed_surrogate_bands",
     "qed_surrogate_forward", "qed_surrogate_grad", "qed_surrogate_sample", "qed_surrogate_destroy",
-    "qed_schwinger_rate", "qed_schwinger_pairs", "qed_push",
+    "qed_schwinger_rate", "qed_schwinger_pairs", "qed_push", "qed_traffic_calibrate",
     "qed_last_error", "qed_version",
 )
 
@@ -141,6 +141,7 @@ def lib():
             "qed_schwinger_rate": [vp, P(CellsC), vp, vp],
             "qed_schwinger_pairs": [vp, P(CellsC), d, d, d, u64, u64, P(AppendC), P(AppendC), vp],
             "qed_push": [vp, P(ParticlesC), vp, vp, vp, P(FieldC), d, d, vp],
+            "qed_traffic_calibrate": [vp, vp, i64, i32, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -383,6 +384,12 @@ def step_noalloc(ctx, desc: StepDesc, stream=None):
     """qed_step_noalloc: the same step with the library's fixed per-GPU
     scratch (ctx may be None: SI units, current device)."""
     check(lib().qed_step_noalloc(ctx.h if ctx is not None else None, C.byref(desc.c), _stream(stream)))
+
+
+def traffic_calibrate(src, dst, n_bytes, mode, stream=None):
+    """qed_traffic_calibrate: stream n_bytes with the step's access pattern
+    (mode 0 read src, 1 write dst, 2 copy), for counter calibration."""
+    check(lib().qed_traffic_calibrate(_ptr(src), _ptr(dst), int(n_bytes), int(mode), _stream(stream)))
 
 
 def version():

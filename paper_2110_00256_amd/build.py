@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libqedmi.so")
 
-SOURCES = ["api.cpp", "table.cpp", "tablegen.cpp", "step.hip", "surrogate.hip", "schwinger.hip", "tablegen_device.hip", "push.hip", "chunks.hip", "noalloc.hip"]
+SOURCES = ["api.cpp", "table.cpp", "tablegen.cpp", "step.hip", "surrogate.hip", "schwinger.hip", "tablegen_device.hip", "push.hip", "chunks.hip", "noalloc.hip", "calibrate.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -226,7 +226,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     // streaming), then their sample (BW xi, QS xi)
     T* s_chi = reinterpret_cast<T*>(evlist + kChunk);
     __shared__ unsigned long long kmask[kMasks];
-    __shared__ unsigned long long smask[kSurr ? kMasks : 1];   // events sampled by the surrogate
+    // surrogate path: per event, whether the network sampled it; per wave, the
+    // events whose chi lies in a band the network serves
+    __shared__ uint8_t s_have[kSurr ? kChunk : 1];
+    __shared__ uint16_t s_slist[kSurr ? kChunk : 1];
     __shared__ int kpref[kMasks];
     __shared__ int s_wcnt[kBlock / 64];
     __shared__ int s_lbp[kBlock / 64];          // look-back scratch
@@ -396,44 +399,58 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             return evlist[w * kWaveSpan + e - pw];
         };
 
-        // ---------------- surrogate pass (FP32 data only): the network's
-        // sample overwrites the event's LDS chi word and its smask bit is
-        // set; events outside the trained domain or in a wave whose probe
-        // failed keep chi and use the table.  A pass of its own, so that the
-        // network's registers are not live in the event phase.  A wave
-        // with no event left skips the rest (the network needs whole waves).
+        // ---------------- surrogate pass (FP32 data only).  Each wave
+        // gathers, in order, those of its events (e = wave 64 + lane + 256 r)
+        // whose chi lies in a band the network serves, then runs the network
+        // over them 64 at a time: every batch is full, and events the
+        // network does not serve cost it nothing.  The network's sample
+        // overwrites the event's LDS chi word and s_have[e] is set; events
+        // outside its domain or in a batch whose probe failed keep chi and use
+        // the table.  A pass of its own, so that the network's registers are
+        // not live in the event phase.
         bool surr_on = false;
         if constexpr (kSurr && sizeof(T) == 4) {
             surr_on = photon ? a.use_bw_surr : a.use_qs_surr;
             if (surr_on) {
                 const SurrogateDev& sv = photon ? a.bw_surr : a.qs_surr;
-                // one wave batch in probe_every is probed (rounds staggered
-                // by chunk); after a failed probe the wave keeps the table for
-                // the rest of the chunk
-                bool failed_before = false;
+                uint16_t* wlist = s_slist + wave * kWaveSpan;   // at most kChunk / 4 events per wave
+                int ns = 0;
                 for (int e0 = 0; e0 + wave * 64 < total; e0 += kBlock) {
                     const int e = e0 + tid;
                     const bool valid = e < total;
+                    if (valid) s_have[e] = 0;
+                    const bool served = valid && surr_serves_chi(sv, s_chi[ev_loc(e)]);
+                    const unsigned long long m = __ballot(served);
+                    if (served) wlist[ns + static_cast<int>(bits_below(m))] = static_cast<uint16_t>(e);
+                    ns += __popcll(m);
+                }
+                // one batch in probe_every is probed (staggered by chunk and
+                // wave); after a failed probe the wave keeps the table for the
+                // rest of the chunk
+                bool failed_before = false;
+                for (int b0 = 0; b0 < ns; b0 += 64) {
+                    const int i = b0 + static_cast<int>(lane);
+                    const bool valid = i < ns;
+                    const int e = valid ? wlist[i] : 0;
                     const int le = valid ? ev_loc(e) : 0;
                     const float chi = valid ? s_chi[le] : 1.f;
                     float r = 0.5f;
                     if (valid)
                         r = static_cast<float>(dev::draws(a.seed, static_cast<unsigned long long>(S.id_base + c.begin + le),
                                                           a.step, static_cast<unsigned long long>(S.species), 0ULL).u[0]);
-                    const bool probe = ((k + (e0 >> 8)) % sv.probe_every) == 0;
+                    const bool probe = ((k + wave + (b0 >> 6)) % sv.probe_every) == 0;
                     bool batch, failed;
-                    float v = surr_wave_sample(sv, photon ? a.bw : a.qs, valid, chi, r, probe, batch,
-                                               failed);
+                    float v = surr_wave_sample(sv, photon ? a.bw : a.qs, valid, chi, r, probe, batch, failed);
                     failed_before = failed_before || failed;
                     if (failed_before) v = __builtin_nanf("");
                     if (lane == 0 && batch) {
                         ++n_surr_batches;
                         if (failed_before) ++n_surr_fallbacks;
                     }
-                    const bool have = valid && !__builtin_isnan(v);
-                    if (have) s_chi[le] = v;
-                    const unsigned long long m = __ballot(have);
-                    if (lane == 0) smask[(e0 >> 6) + wave] = m;
+                    if (valid && !__builtin_isnan(v)) {
+                        s_chi[le] = v;
+                        s_have[e] = 1;
+                    }
                 }
                 __syncthreads();
             }
@@ -458,7 +475,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             return dev::dexp(have ? cs : dev::sample_qs_lnxi_lr<T>(a.qs, cs, lr));
         };
         auto is_surr = [&](int e) {
-            return surr_on && ((smask[e >> 6] >> (e & 63)) & 1ULL);
+            if constexpr (kSurr) return surr_on && s_have[e] != 0;
+            else return false;
         };
         int prods = total;
         if (!thresh) {

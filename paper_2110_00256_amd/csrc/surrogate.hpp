@@ -89,11 +89,16 @@ __device__ __forceinline__ void surr_features(const SurrogateDev& s, float chi, 
     }
 }
 
-// Inside the trained domain?  (Otherwise the table is used.)
-__device__ __forceinline__ bool surr_inside(const SurrogateDev& s, float chi, float u) {
+// chi inside the trained range and in a band the network serves?
+__device__ __forceinline__ bool surr_serves_chi(const SurrogateDev& s, float chi) {
     if (!(chi >= s.chi_lo && chi <= s.chi_hi)) return false;
     const int band = min(kSurrBands - 1, max(0, static_cast<int>((logf(chi) - s.ln_chi_lo) * s.band_inv_w)));
-    if (!((s.band_mask >> band) & 1ULL)) return false;
+    return (s.band_mask >> band) & 1ULL;
+}
+
+// Inside the trained domain?  (Otherwise the table is used.)
+__device__ __forceinline__ bool surr_inside(const SurrogateDev& s, float chi, float u) {
+    if (!surr_serves_chi(s, chi)) return false;
     if (s.process == 1) return u >= kSurrUMin && u <= kSurrUMaxQs;
     const float r = u <= 0.5f ? u : 1.0f - u;
     return r >= kSurrUMin;
