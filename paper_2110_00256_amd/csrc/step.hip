@@ -164,15 +164,16 @@ __device__ __forceinline__ void write_product(const AppendDev& o, int64_t slot, 
 // `failed` is set.  Returns the network-side sample (QS: ln xi; BW: xi), or
 // NAN where the caller must use the table; `batch` tells whether the
 // network ran for this wave.
-__device__ __forceinline__ float surr_wave_sample(const SurrogateDev& sv, const TableDev& tab, bool valid, float chi,
-                                                  float u, bool probe, bool& batch, bool& failed) {
+__device__ __forceinline__ float surr_wave_sample(const SurrogateDev& sv, const SurrLds* lw, const TableDev& tab,
+                                                  bool valid, float chi, float u, bool probe, bool& batch,
+                                                  bool& failed) {
     float x0 = 0.f, x1 = 0.f;
     const bool inside = valid && surr_inputs(sv, chi, u, x0, x1);
     const unsigned long long in_mask = __ballot(inside);
     batch = in_mask != 0ULL;
     failed = false;
     if (!batch) return __builtin_nanf("");
-    const float y = surr_forward_wave(sv, x0, x1);
+    const float y = surr_forward_wave_lds(lw, x0, x1);
     if (!probe) return inside ? surr_output(sv, chi, u, y) : __builtin_nanf("");
     // probe: the first lane with an in-domain event
     const unsigned probe_lane = static_cast<unsigned>(__builtin_ctzll(in_mask));
@@ -225,6 +226,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     // chi of the chunk's event particles at their chunk index (written while
     // streaming), then their sample (BW xi, QS xi)
     T* s_chi = reinterpret_cast<T*>(evlist + kChunk);
+    // surrogate path: the weights of the process whose chunk is in hand
+    SurrLds* s_net = reinterpret_cast<SurrLds*>(
+        lds_raw + ((reinterpret_cast<unsigned char*>(s_chi + kChunk) - lds_raw + 15) & ~static_cast<ptrdiff_t>(15)));
+    int staged = -1;
     __shared__ unsigned long long kmask[kMasks];
     // surrogate path: per event, whether the network sampled it; per wave, the
     // events whose chi lies in a band the network serves
@@ -305,10 +310,13 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             // FP64: one particle per lane at a time, the next one's ten
             // loads issued before the current one is evaluated (stores in
             // between could alias them, so the compiler would not hoist the
-            // loads itself); FP32: four particles' loads issued together.
+            // loads itself); FP32: four particles' loads issued together, two
+            // in the surrogate kernel (whose network pass leaves fewer
+            // registers to the stream: with four, values live across the
+            // chunk were spilled and reloaded inside this loop).
             // Lanes past the end load the chunk's first particle and drop it.
             constexpr bool kPipe = sizeof(T) == 8;
-            constexpr int kBatch = sizeof(T) == 8 ? 1 : 4;
+            constexpr int kBatch = sizeof(T) == 8 ? 1 : (kSurr ? 2 : 4);
             constexpr int kIters = kWaveSpan / 64;
             static_assert(kIters % kBatch == 0, "a wave's span must be a whole number of batches");
             auto load_batch = [&](int it, T (&v)[kBatch][10]) {
@@ -316,9 +324,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 for (int b = 0; b < kBatch; ++b) {
                     const int loc = wbase + (it + b) * 64 + static_cast<int>(lane);
                     const int64_t j = c.begin + (loc < c.len ? loc : 0);
-                    // u with ordinary loads (phase 2b gathers the events' u
-                    // again, and finds part of its lines still cached), the
-                    // fields and tau non-temporal (read once)
+                    // u with ordinary loads (the event pass gathers the
+                    // events' u again, and finds part of its lines still
+                    // cached), the fields and tau non-temporal (read once)
 #pragma unroll
                     for (int q = 0; q < 10; ++q) v[b][q] = q < 3 ? ld<T>(S.p[q], j) : ldnt<T>(S.p[q], j);
                 }
@@ -413,6 +421,12 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             surr_on = photon ? a.use_bw_surr : a.use_qs_surr;
             if (surr_on) {
                 const SurrogateDev& sv = photon ? a.bw_surr : a.qs_surr;
+                // this process's weights into LDS (once per block and process)
+                if (staged != static_cast<int>(photon)) {
+                    surr_stage(sv, s_net, tid, kBlock);
+                    staged = static_cast<int>(photon);
+                    __syncthreads();
+                }
                 uint16_t* wlist = s_slist + wave * kWaveSpan;   // at most kChunk / 4 events per wave
                 int ns = 0;
                 for (int e0 = 0; e0 + wave * 64 < total; e0 += kBlock) {
@@ -440,7 +454,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                                                           a.step, static_cast<unsigned long long>(S.species), 0ULL).u[0]);
                     const bool probe = ((k + wave + (b0 >> 6)) % sv.probe_every) == 0;
                     bool batch, failed;
-                    float v = surr_wave_sample(sv, photon ? a.bw : a.qs, valid, chi, r, probe, batch, failed);
+                    float v = surr_wave_sample(sv, s_net, photon ? a.bw : a.qs, valid, chi, r, probe, batch, failed);
                     failed_before = failed_before || failed;
                     if (failed_before) v = __builtin_nanf("");
                     if (lane == 0 && batch) {
@@ -694,8 +708,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
 
 // Both kernels get a register budget of three waves per SIMD: the streaming
 // phase needs waves in flight more than registers (measured 9% faster in
-// FP32 than the compiler's own choice for the table path, and 12% for the
-// surrogate path over a budget of two waves).
+// FP32 than the compiler's own choice for the table path; for the surrogate
+// path with two-particle batches, 1.00 ms against 1.14 ms with a budget of
+// two waves on the cone workload).
 constexpr int kTableWavesPerEu = 3;
 constexpr int kSurrWavesPerEu = 3;
 
@@ -802,7 +817,9 @@ __global__ void __launch_bounds__(256) table_sample_kernel(TableCallArgs a) {
 size_t step_lds_bytes(const StepArgs& a, size_t elem) {
     const int nbw = a.bw.n_chi > 0 ? a.bw.n_chi : 0;
     const int nqs = a.qs.n_chi > 0 ? a.qs.n_chi : 0;
-    return elem * (((nbw + 1) & ~1) + ((nqs + 1) & ~1)) + sizeof(uint16_t) * kChunk + elem * kChunk;
+    const bool surr = elem == 4 && (a.use_bw_surr || a.use_qs_surr);
+    return elem * (((nbw + 1) & ~1) + ((nqs + 1) & ~1)) + sizeof(uint16_t) * kChunk + elem * kChunk +
+           (surr ? kSurrLdsBytes + 16 : 0);
 }
 
 template <typename T, bool kSurr>

@@ -204,4 +204,77 @@ __device__ __forceinline__ float surr_forward_wave(const SurrogateDev& s, float 
     return y;
 }
 
+// One network's weights in the layout that the fused step's forward pass
+// reads from LDS: the 16 BF16 fragments of W2 (fragment 4 nt + ks, lane l:
+// W2[16 nt + (l & 15)][16 ks + 4 (l >> 4) + 0..3], the layer-2 A operand),
+// each lane's layer-1 operand for the four hidden-unit blocks, b2, w3, b3.
+// Every fragment read is 64 consecutive 8-byte words (no bank conflict), so
+// the weights need not stay in registers between batches.
+struct alignas(16) SurrLds {
+    surr_v4s w2f[16][64];
+    float a1[4][64];
+    float b2[64];
+    float w3[64];
+    float b3[4];
+};
+constexpr size_t kSurrLdsBytes = sizeof(SurrLds);
+
+// Fill `L` from the device parameters (all threads of the block take part;
+// the caller synchronises before the first forward pass).
+__device__ __forceinline__ void surr_stage(const SurrogateDev& s, SurrLds* L, int tid, int nthreads) {
+    const float* p = s.p;
+    for (int i = tid; i < 16 * 64; i += nthreads) {
+        const int f = i >> 6, l = i & 63, nt = f >> 2, ks = f & 3;
+        L->w2f[f][l] = *reinterpret_cast<const surr_v4s*>(s.w2 + (nt * 16 + (l & 15)) * 64 + ks * 16 + 4 * (l >> 4));
+    }
+    for (int i = tid; i < 4 * 64; i += nthreads) {
+        const int ks = i >> 6, l = i & 63, grp = l >> 4, h = ks * 16 + (l & 15);
+        L->a1[ks][l] = grp == 0 ? p[kOffW1 + 2 * h] : grp == 1 ? p[kOffW1 + 2 * h + 1] : grp == 2 ? p[kOffB1 + h] : 0.0f;
+    }
+    for (int i = tid; i < 64; i += nthreads) {
+        L->b2[i] = p[kOffB2 + i];
+        L->w3[i] = p[kOffW3 + i];
+    }
+    if (tid < 4) L->b3[tid] = p[kOffB3];
+}
+
+// surr_forward_wave with the weights read from a staged SurrLds, fragment by
+// fragment as the MFMAs need them: the same operations in the same order, so
+// the same output bits.
+__device__ __forceinline__ float surr_forward_wave_lds(const SurrLds* L, float x0, float x1) {
+    const int lane = static_cast<int>(__lane_id());
+    const int col = lane & 15, grp = lane >> 4;
+    float y = 0.0f;
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) {
+        const float sx0 = __shfl(x0, q * 16 + col);
+        const float sx1 = __shfl(x1, q * 16 + col);
+        const float bx = grp == 0 ? sx0 : grp == 1 ? sx1 : grp == 2 ? 1.0f : 0.0f;
+        surr_v4s h1[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const surr_v4f zero = {0.0f, 0.0f, 0.0f, 0.0f};
+            const surr_v4f z = __builtin_amdgcn_mfma_f32_16x16x4f32(L->a1[ks][lane], bx, zero, 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) h1[ks][e] = surr_bf16(surr_silu(z[e]));
+        }
+        float part = 0.0f;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            surr_v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(L->w2f[nt * 4 + ks][lane], h1[ks], acc, 0, 0, 0);
+            const surr_v4f b2v = *reinterpret_cast<const surr_v4f*>(L->b2 + nt * 16 + 4 * grp);
+            const surr_v4f w3v = *reinterpret_cast<const surr_v4f*>(L->w3 + nt * 16 + 4 * grp);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) part += w3v[e] * surr_silu(acc[e] + b2v[e]);
+        }
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (grp == q) y = part + L->b3[0];
+    }
+    return y;
+}
+
 }  // namespace qedmi
