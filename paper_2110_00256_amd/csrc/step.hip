@@ -231,10 +231,6 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
         lds_raw + ((reinterpret_cast<unsigned char*>(s_chi + kChunk) - lds_raw + 15) & ~static_cast<ptrdiff_t>(15)));
     int staged = -1;
     __shared__ unsigned long long kmask[kMasks];
-    // surrogate path: per event, whether the network sampled it; per wave, the
-    // events whose chi lies in a band the network serves
-    __shared__ uint8_t s_have[kSurr ? kChunk : 1];
-    __shared__ uint16_t s_slist[kSurr ? kChunk : 1];
     __shared__ int kpref[kMasks];
     __shared__ int s_wcnt[kBlock / 64];
     __shared__ int s_lbp[kBlock / 64];          // look-back scratch
@@ -410,68 +406,42 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             return evlist[w * kWaveSpan + e - pw];
         };
 
-        // ---------------- surrogate pass (FP32 data only).  Each wave
-        // gathers, in order, those of its events (e = wave 64 + lane + 256 r)
-        // whose chi lies in a band the network serves, then runs the network
-        // over them 64 at a time: every batch is full, and events the
-        // network does not serve cost it nothing.  The network's sample
-        // overwrites the event's LDS chi word and s_have[e] is set; events
-        // outside its domain or in a batch whose probe failed keep chi and use
-        // the table.  A pass of its own, so that the network's registers are
-        // not live in the event phase.
+        // ---------------- surrogate (FP32 data only): the network runs inside
+        // the event rounds, each wave over its 64 events of the round, on the
+        // round's own draw; its weights are staged in LDS once per block and
+        // process.  Events outside its served domain, and those of a wave
+        // whose probe failed earlier in the chunk, use the table.
         bool surr_on = false;
+        bool surr_failed = false;
         if constexpr (kSurr && sizeof(T) == 4) {
             surr_on = photon ? a.use_bw_surr : a.use_qs_surr;
-            if (surr_on) {
-                const SurrogateDev& sv = photon ? a.bw_surr : a.qs_surr;
-                // this process's weights into LDS (once per block and process)
-                if (staged != static_cast<int>(photon)) {
-                    surr_stage(sv, s_net, tid, kBlock);
-                    staged = static_cast<int>(photon);
-                    __syncthreads();
-                }
-                uint16_t* wlist = s_slist + wave * kWaveSpan;   // at most kChunk / 4 events per wave
-                int ns = 0;
-                for (int e0 = 0; e0 + wave * 64 < total; e0 += kBlock) {
-                    const int e = e0 + tid;
-                    const bool valid = e < total;
-                    if (valid) s_have[e] = 0;
-                    const bool served = valid && surr_serves_chi(sv, s_chi[ev_loc(e)]);
-                    const unsigned long long m = __ballot(served);
-                    if (served) wlist[ns + static_cast<int>(bits_below(m))] = static_cast<uint16_t>(e);
-                    ns += __popcll(m);
-                }
-                // one batch in probe_every is probed (staggered by chunk and
-                // wave); after a failed probe the wave keeps the table for the
-                // rest of the chunk
-                bool failed_before = false;
-                for (int b0 = 0; b0 < ns; b0 += 64) {
-                    const int i = b0 + static_cast<int>(lane);
-                    const bool valid = i < ns;
-                    const int e = valid ? wlist[i] : 0;
-                    const int le = valid ? ev_loc(e) : 0;
-                    const float chi = valid ? s_chi[le] : 1.f;
-                    float r = 0.5f;
-                    if (valid)
-                        r = static_cast<float>(dev::draws(a.seed, static_cast<unsigned long long>(S.id_base + c.begin + le),
-                                                          a.step, static_cast<unsigned long long>(S.species), 0ULL).u[0]);
-                    const bool probe = ((k + wave + (b0 >> 6)) % sv.probe_every) == 0;
-                    bool batch, failed;
-                    float v = surr_wave_sample(sv, s_net, photon ? a.bw : a.qs, valid, chi, r, probe, batch, failed);
-                    failed_before = failed_before || failed;
-                    if (failed_before) v = __builtin_nanf("");
-                    if (lane == 0 && batch) {
-                        ++n_surr_batches;
-                        if (failed_before) ++n_surr_fallbacks;
-                    }
-                    if (valid && !__builtin_isnan(v)) {
-                        s_chi[le] = v;
-                        s_have[e] = 1;
-                    }
-                }
+            if (surr_on && staged != static_cast<int>(photon)) {
+                surr_stage(photon ? a.bw_surr : a.qs_surr, s_net, tid, kBlock);
+                staged = static_cast<int>(photon);
                 __syncthreads();
             }
         }
+        // the network's sample for this lane's event (QS: ln xi, BW: xi), NaN
+        // where the table samples; called by every lane of the wave
+        auto net_sample = [&](bool valid, T cs, double u0, int round) -> float {
+            if constexpr (kSurr && sizeof(T) == 4) {
+                if (!surr_on) return __builtin_nanf("");
+                const SurrogateDev& sv = photon ? a.bw_surr : a.qs_surr;
+                const bool probe = ((k + wave + round) % sv.probe_every) == 0;
+                bool batch, failed;
+                float v = surr_wave_sample(sv, s_net, photon ? a.bw : a.qs, valid, static_cast<float>(cs),
+                                           static_cast<float>(u0), probe, batch, failed);
+                surr_failed = surr_failed || failed;
+                if (surr_failed) v = __builtin_nanf("");
+                if (lane == 0 && batch) {
+                    ++n_surr_batches;
+                    if (surr_failed) ++n_surr_fallbacks;
+                }
+                return v;
+            } else {
+                return __builtin_nanf("");
+            }
+        };
 
         // ---------------- events.  Per event: the draws (Philox block 0 of
         // the parent), the inverse-CDF sample (table search on chi, or the
@@ -490,10 +460,6 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             }
             const T lr = dev::qs_log_uniform<T>(u0);
             return dev::dexp(have ? cs : dev::sample_qs_lnxi_lr<T>(a.qs, cs, lr));
-        };
-        auto is_surr = [&](int e) {
-            if constexpr (kSurr) return surr_on && s_have[e] != 0;
-            else return false;
         };
         int prods = total;
         if (!thresh) {
@@ -530,7 +496,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 const dev::Draws d = dev::draws(a.seed, static_cast<unsigned long long>(parent), a.step,
                                                 static_cast<unsigned long long>(S.species), 0ULL);
                 const T cs = valid ? s_chi[le] : T(1);
-                const T xi = valid ? sample_of(is_surr(e), cs, d.u[0]) : T(0);
+                const float nv = net_sample(valid, cs, d.u[0], e0 / kBlock);
+                const bool have = valid && !__builtin_isnan(nv);
+                const T xi = valid ? sample_of(have, have ? static_cast<T>(nv) : cs, d.u[0]) : T(0);
                 // optical depths from uniforms 1 and 2: BW electron and
                 // positron; QS parent (redrawn) and photon
                 const T t1 = static_cast<T>(-log(d.u[1]));
@@ -601,7 +569,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 const T cs = valid ? s_chi[le] : T(1);
                 const double u0 = dev::draws(a.seed, static_cast<unsigned long long>(S.id_base + c.begin + le),
                                              a.step, static_cast<unsigned long long>(S.species), 0ULL).u[0];
-                const T xi = valid ? sample_of(is_surr(e), cs, u0) : T(0);
+                const float nv = net_sample(valid, cs, u0, e0 / kBlock);
+                const bool have = valid && !__builtin_isnan(nv);
+                const T xi = valid ? sample_of(have, have ? static_cast<T>(nv) : cs, u0) : T(0);
                 if (valid) s_chi[le] = xi;
             }
             __syncthreads();

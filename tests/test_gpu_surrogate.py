@@ -295,6 +295,62 @@ def test_step_with_surrogate_probe_and_counts(ctx, tables):
     assert ks < 0.1
 
 
+def test_step_with_surrogate_and_photon_threshold(ctx, tables):
+    """The surrogate inside the thresholded photon emission (Sec. 4: only
+    photons above a minimum energy are created).  With every probe failing
+    (tolerance 0) the step must equal the table path bit for bit; with the
+    trained network the event flags equal the table path's (they do not
+    depend on the sample), every kept photon is above the threshold and the
+    parents are the flagged leptons in order."""
+    bw, qs = tables
+    cfg_q = Q.Surrogate.cfg(Q.QS, 1e-3, 1e3, n_samples=1 << 21, steps=3000, probe_tol=1.0)
+    sq, _ = Q.Surrogate.train(ctx, qs, cfg_q)
+    sq0 = Q.Surrogate.from_host(qs, Q.Surrogate.cfg(Q.QS, 1e-3, 1e3, probe_tol=0.0, probe_every=1), sq.params())
+    el, ph = QI.cone_population(seed=9, n=1 << 18)
+    threshold = 50.0   # photon energy floor, m c^2
+    results = {}
+    for name, surr in (("table", None), ("probe0", sq0), ("surr", sq)):
+        d = []
+        for pop in (el, ph):
+            t = {k: torch.as_tensor(v).to("cuda", torch.float32) for k, v in pop.items()}
+            t["tau"] = torch.empty_like(t["ux"])
+            d.append(t)
+        pe, pg = Q.particles(d[0], Q.ELECTRON, 0), Q.particles(d[1], Q.PHOTON, 1 << 18)
+        Q.init_optical_depth(ctx, pe, 9)
+        Q.init_optical_depth(ctx, pg, 9)
+        bufs = [Q.AppendBuffer(1 << 18, torch.float32) for _ in range(3)]
+        stats = torch.zeros(Q.STATS_LEN, dtype=torch.int64, device="cuda")
+        fe = torch.zeros(1 << 18, dtype=torch.uint8, device="cuda")
+        desc = Q.StepDesc([pe, pg], bw=bw, qs=qs, photons=bufs[0], electrons=bufs[1], positrons=bufs[2],
+                          flags=[fe, None], stats=stats, dt=1e-16, seed=9, photon_min_energy=threshold,
+                          qs_surrogate=surr)
+        Q.step(ctx, desc)
+        torch.cuda.synchronize()
+        n = int(bufs[0].count.item())
+        results[name] = dict(flags=fe.cpu().numpy(), stats=stats.cpu().numpy(), n=n,
+                             parent=bufs[0].parent[:n].cpu().numpy(),
+                             u=np.stack([bufs[0].a[k][:n].cpu().numpy() for k in ("ux", "uy", "uz")], 1),
+                             state={k: d[0][k].cpu().numpy() for k in ("ux", "uy", "uz", "tau")})
+    t0, p0, s1 = results["table"], results["probe0"], results["surr"]
+    assert t0["n"] > 0 and t0["n"] < int(t0["flags"].sum())   # the threshold drops some photons
+    assert p0["stats"][Q.STAT_SURR_BATCHES] > 0
+    assert p0["stats"][Q.STAT_SURR_FALLBACK] == p0["stats"][Q.STAT_SURR_BATCHES]
+    assert p0["n"] == t0["n"]
+    np.testing.assert_array_equal(p0["parent"], t0["parent"])
+    np.testing.assert_array_equal(p0["u"], t0["u"])
+    for k in ("ux", "uy", "uz", "tau"):
+        np.testing.assert_array_equal(p0["state"][k], t0["state"][k])
+    np.testing.assert_array_equal(s1["flags"], t0["flags"])
+    assert s1["stats"][Q.STAT_SURR_BATCHES] > 0
+    assert s1["n"] > 0
+    # kept photons: above the threshold (FP32 energy, one rounding of slack),
+    # parents strictly increasing and all flagged
+    energy = np.linalg.norm(s1["u"].astype(np.float64), axis=1)
+    assert energy.min() >= threshold * (1 - 1e-6)
+    assert np.all(np.diff(s1["parent"]) > 0)
+    assert np.all(s1["flags"][s1["parent"]] == 1)
+
+
 @pytest.mark.parametrize("proc", [Q.QS, Q.BW])
 def test_gain_over_table(ctx, tables512, bench_trained, proc):
     """What the trained network gains over the table it replaces, and where.
