@@ -30,9 +30,10 @@
  *   - Sequential, parent-ordered product append.
  *
  * Readings of the paper taken where it is silent or inconsistent are listed
- * at each function.  Parity unpinned: the out-of-table rules for T below
- * chi_min / above chi_max and the QS extrapolation below the first CDF knot
- * are this library's reading and have no pin beyond their own definition.
+ * at each function.  The out-of-table rules for T below chi_min / above
+ * chi_max and the QS extrapolation below the first CDF knot are this
+ * library's reading; each is pinned against the exact integral it continues
+ * (tests/test_oracle_statistics.py).
  */
 #include <math.h>
 #include <stdint.h>

@@ -10,6 +10,9 @@
 * Total rates (Sec. 2.1 BW rate, Sec. 2.2 QS rate, Sec. 3 optical depth):
   the fraction of particles without an event after k steps is
   exp(-rate k dt), with the rate taken from the integrated cross section.
+* The continuations outside the tables (Sec. 3.1, 3.2 leave them open):
+  the BW rate's asymptotic rules and the QS CDF below its first knot follow
+  the exact integrals with the error the neglected terms predict.
 * The classical radiation drag below the minimum quantum parameter (Sec. 6):
   its power equals Larmor's formula in SI (the synchrotron and linear
   cases); iterating it in a fixed magnetic field converges at first order
@@ -281,3 +284,32 @@ def test_qs_extrapolation_below_first_knot_is_exact_cdf(chi):
         # spectrum from 0 to xi
         _, low = O.table_row(O.QS, chi, 3, xi)
         assert low[0] == pytest.approx(row[0] + math.log(xi / xi_min) / 3.0, abs=1e-5)
+
+
+def test_bw_rate_out_of_table_rules_approach_exact_T():
+    """The BW rate outside the tabulated chi range (Sec. 3.1 leaves it open;
+    the runtime continues ln T with the asymptotes of the integral, matched
+    at the table edge).  Against T by quadrature (Sec. 2.1):
+    * above chi_max the rule keeps the large-chi law T ~ chi^(-1/3); the
+      neglected term of T's expansion is O(chi^(-2/3)), so at a fixed
+      multiple of chi_max the relative error falls by about 10^(2/3) per
+      decade of chi_max (a wrong exponent would leave it constant);
+    * below chi_min the rule keeps the small-chi law
+      T ~ exp(-8/(3 chi)); the neglected prefactor term is O(chi), so at a
+      fixed fraction of chi_min the error halves with chi_min (a wrong
+      coefficient of 1/chi would grow it exponentially)."""
+    r0 = O.rate_prefactor()
+
+    def err(table, c):
+        return table.rate(c, 1.0) / (r0 * c) / O.bw_T(c) - 1.0
+
+    above = {cm: [err(O.Table(O.BW, 1e-2, cm, 8, 8), f * cm) for f in (2.0, 4.0)] for cm in (1e2, 1e3)}
+    for i in range(2):
+        assert above[1e3][i] < 0.0 and abs(above[1e3][i]) < 1.2e-2
+        ratio = above[1e2][i] / above[1e3][i]
+        assert 10 ** (2 / 3) * 0.9 < ratio < 10 ** (2 / 3) * 1.2
+    below = {cm: [err(O.Table(O.BW, cm, 1.0, 8, 8), f * cm) for f in (0.75, 0.5)] for cm in (0.04, 0.02)}
+    for i in range(2):
+        assert below[0.02][i] < 0.0 and abs(below[0.02][i]) < 2e-3
+        ratio = below[0.04][i] / below[0.02][i]
+        assert 1.9 < ratio < 2.1
