@@ -453,5 +453,16 @@ __device__ __forceinline__ T bw_folded_uniform(double u, bool& electron) {
     return static_cast<T>(electron ? u : 1.0 - u);
 }
 
+// A redrawn optical depth -ln u.  FP32 takes the logarithm of the rounded
+// uniform: its absolute error stays near the FP32 spacing of u (about 6e-8
+// where u -> 1 and t -> 0, and relative 6e-8 where t is large), which is
+// what the FP32 path's optical depths carry anyway.
+template <typename T>
+__device__ __forceinline__ T neg_log_uniform(double u);
+template <>
+__device__ __forceinline__ double neg_log_uniform<double>(double u) { return -log(u); }
+template <>
+__device__ __forceinline__ float neg_log_uniform<float>(double u) { return -logf(static_cast<float>(u)); }
+
 }  // namespace dev
 }  // namespace qedmi

@@ -501,8 +501,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 const T xi = valid ? sample_of(have, have ? static_cast<T>(nv) : cs, d.u[0]) : T(0);
                 // optical depths from uniforms 1 and 2: BW electron and
                 // positron; QS parent (redrawn) and photon
-                const T t1 = static_cast<T>(-log(d.u[1]));
-                const T t2 = static_cast<T>(-log(d.u[2]));
+                const T t1 = dev::neg_log_uniform<T>(d.u[1]);
+                const T t2 = dev::neg_log_uniform<T>(d.u[2]);
                 T pa[3], pb[3];   // BW: the electron's and positron's u; QS: the photon's u
                 if (photon) {
                     const bool esel = d.u[0] <= 0.5;   // on the 53-bit uniform, as the fold
@@ -624,8 +624,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 const dev::Draws d = dev::draws(a.seed, static_cast<unsigned long long>(parent), a.step,
                                                 static_cast<unsigned long long>(S.species), 0ULL);
                 const T xi = s_chi[le];
-                const T t1 = static_cast<T>(-log(d.u[1]));
-                const T t2 = static_cast<T>(-log(d.u[2]));
+                const T t1 = dev::neg_log_uniform<T>(d.u[1]);
+                const T t2 = dev::neg_log_uniform<T>(d.u[2]);
                 const double dx = ux, dy = uy, dz = uz;
                 const double u2 = dx * dx + dy * dy + dz * dz;
                 const T gg = static_cast<T>(u2 / (sqrt(1.0 + u2) + 1.0)) * xi;
