@@ -14,6 +14,21 @@ namespace qedmi {
 namespace dev {
 
 // ------------------------------------------------------------------ Philox
+// The 128-bit product m c as (lo, hi), from four 32x32->64 partial products
+// chained through their carries: each is one v_mad_u64_u32, and no separate
+// 32-bit low multiplies are needed (the compiler's own lowering of a 64-bit
+// product and its high half used a third more quarter-rate instructions).
+__device__ __forceinline__ void mulhilo64(unsigned long long m, unsigned long long c, unsigned long long& lo,
+                                          unsigned long long& hi) {
+    const unsigned ml = static_cast<unsigned>(m), mh = static_cast<unsigned>(m >> 32);
+    const unsigned cl = static_cast<unsigned>(c), ch = static_cast<unsigned>(c >> 32);
+    const unsigned long long p0 = static_cast<unsigned long long>(ml) * cl;
+    const unsigned long long p1 = static_cast<unsigned long long>(ml) * ch + (p0 >> 32);
+    const unsigned long long p2 = static_cast<unsigned long long>(mh) * cl + static_cast<unsigned>(p1);
+    hi = static_cast<unsigned long long>(mh) * ch + (p1 >> 32) + (p2 >> 32);
+    lo = (p2 << 32) | static_cast<unsigned>(p0);
+}
+
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 64x64->128 multiplies with Weyl-sequence key bumps.
 __device__ __forceinline__ void philox4x64_10(unsigned long long& c0, unsigned long long& c1,
@@ -23,8 +38,9 @@ __device__ __forceinline__ void philox4x64_10(unsigned long long& c0, unsigned l
     constexpr unsigned long long kW0 = 0x9E3779B97F4A7C15ULL, kW1 = 0xBB67AE8584CAA73BULL;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const unsigned long long lo0 = kM0 * c0, hi0 = __umul64hi(kM0, c0);
-        const unsigned long long lo1 = kM1 * c2, hi1 = __umul64hi(kM1, c2);
+        unsigned long long lo0, hi0, lo1, hi1;
+        mulhilo64(kM0, c0, lo0, hi0);
+        mulhilo64(kM1, c2, lo1, hi1);
         const unsigned long long n0 = hi1 ^ c1 ^ k0;
         const unsigned long long n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
