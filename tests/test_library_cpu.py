@@ -158,3 +158,18 @@ def test_noalloc_limits_are_refused_before_launch():
     d, keep = _desc_with_tiles(1000, [(0, 0, 600), (0, 500, 1000)])
     assert Q.lib().qed_step_noalloc(None, C.byref(d), None) == Q.QED_ERR_INVALID
     assert "overlap" in Q.lib().qed_last_error().decode()
+
+
+def test_traffic_calibration_arguments_are_checked_before_launch():
+    """The counter-calibration call refuses a bad mode, a byte count that is
+    not a whole number of 8-byte words, and a missing buffer, before any HIP
+    call (so this runs without a GPU); zero bytes is a no-op."""
+    L = Q.lib()
+    L.qed_traffic_calibrate.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+    dummy = C.c_void_p(8)   # never dereferenced: every case below returns before a launch
+    for src, dst, nb, mode in ((dummy, dummy, 64, 5), (dummy, dummy, 64, -1), (dummy, dummy, 12, 0),
+                               (dummy, dummy, -8, 1), (None, dummy, 64, 0), (dummy, None, 64, 1),
+                               (None, dummy, 64, 3)):
+        assert L.qed_traffic_calibrate(src, dst, nb, mode, None) == Q.QED_ERR_INVALID, (nb, mode)
+        assert L.qed_last_error()
+    assert L.qed_traffic_calibrate(None, None, 0, 0, None) == Q.QED_OK
