@@ -2,20 +2,22 @@
 //
 // step_kernel: one persistent launch processes chunks of kChunk particles
 // taken from an atomic ticket counter.  For each chunk:
-//   phase 1  stream the particle SoA (coalesced), compute chi, the total rate
-//            from the 1D table staged in LDS, tau <- tau - rate dt, and the
-//            event predicate tau < 0 (paper Fig. 1, Sec. 3); each wave's
-//            events are recorded as a 64-bit ballot mask in LDS;
-//   list     the masks are prefix-summed (one wave) and expanded with mbcnt
-//            into an ordered list of event indices (dense event processing:
-//            events of the whole chunk are handed to consecutive lanes);
-//   scan     the chunk's product count is published and the exclusive
-//            prefix over earlier chunks of the same product stream obtained
-//            by decoupled look-back (Merrill & Garland 2016); tickets are
-//            taken in chunk order, so every predecessor is already running;
-//   phase 2  each event: Philox draws, inverse-CDF sample (table or MLP
-//            surrogate), product kinematics (Sec. 2.1, 2.2), parent update,
-//            products written at deterministic slots in parent order.
+//   stream   each wave streams its own quarter of the chunk's particle SoA
+//            (coalesced), computes chi, the total rate from the 1D table
+//            staged in LDS, tau <- tau - rate dt and the event predicate
+//            tau < 0 (paper Fig. 1, Sec. 3), and appends its events' chunk
+//            positions, in order, to its own region of an LDS list (ballot,
+//            mbcnt, running count); the events' chi goes to LDS;
+//   counts   one barrier: the four waves' counts give the chunk's event
+//            total, published at once for the decoupled look-back
+//            (Merrill & Garland 2016); tickets are taken in chunk order, so
+//            every predecessor is already running;
+//   events   dense rounds over the chunk's events, one per thread: Philox
+//            draws, inverse-CDF sample (table, or the MLP surrogate on the
+//            round's 64 events of a wave), product kinematics (Sec. 2.1,
+//            2.2), parent update; after the first round the block resolves
+//            the exclusive prefix over earlier chunks of the same product
+//            stream, and products go to deterministic slots in parent order.
 #include <hip/hip_runtime.h>
 
 #include "device_physics.hpp"
@@ -445,7 +447,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
 
         // ---------------- events.  Per event: the draws (Philox block 0 of
         // the parent), the inverse-CDF sample (table search on chi, or the
-        // surrogate's sample already in LDS), the kinematics, the parent's new
+        // surrogate network inside its served bands), the kinematics, the parent's new
         // u and tau, and the products at deterministic slots in parent order:
         // slot = exclusive prefix of the stream's product counts over earlier
         // chunks (decoupled look-back) + the event's rank in this chunk.
