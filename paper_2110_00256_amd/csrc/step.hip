@@ -495,7 +495,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                     if (S.p[10]) nw = ld<T>(S.p[10], jn);
                 }
                 const int64_t parent = S.id_base + j;
-                const dev::Draws d = dev::draws(a.seed, static_cast<unsigned long long>(parent), a.step,
+                const dev::Draws d = dev::draws<sizeof(T) == 4>(a.seed, static_cast<unsigned long long>(parent), a.step,
                                                 static_cast<unsigned long long>(S.species), 0ULL);
                 const T cs = valid ? s_chi[le] : T(1);
                 const float nv = net_sample(valid, cs, d.u[0], e0 / kBlock);
@@ -569,7 +569,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 const bool valid = e < total;
                 const int le = valid ? ev_loc(e) : 0;
                 const T cs = valid ? s_chi[le] : T(1);
-                const double u0 = dev::draws(a.seed, static_cast<unsigned long long>(S.id_base + c.begin + le),
+                const double u0 = dev::draws<sizeof(T) == 4>(a.seed, static_cast<unsigned long long>(S.id_base + c.begin + le),
                                              a.step, static_cast<unsigned long long>(S.species), 0ULL).u[0];
                 const float nv = net_sample(valid, cs, u0, e0 / kBlock);
                 const bool have = valid && !__builtin_isnan(nv);
@@ -623,7 +623,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 const T ux = su * ld<T>(S.p[0], j), uy = su * ld<T>(S.p[1], j), uz = su * ld<T>(S.p[2], j);
                 const T w = S.p[10] ? ld<T>(S.p[10], j) : T(1);
                 const int64_t parent = S.id_base + j;
-                const dev::Draws d = dev::draws(a.seed, static_cast<unsigned long long>(parent), a.step,
+                const dev::Draws d = dev::draws<sizeof(T) == 4>(a.seed, static_cast<unsigned long long>(parent), a.step,
                                                 static_cast<unsigned long long>(S.species), 0ULL);
                 const T xi = s_chi[le];
                 const T t1 = dev::neg_log_uniform<T>(d.u[1]);
