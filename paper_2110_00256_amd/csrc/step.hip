@@ -146,16 +146,20 @@ __device__ long long resolve(const StepArgs& a, int k, const ChunkDesc& c, unsig
     return excl;
 }
 
+// Products, like the parents' updates, are written once and not read again
+// in the step: non-temporal stores keep them from displacing the tables and
+// the events' gathered u and w in L2.
 template <typename T>
 __device__ __forceinline__ void write_product(const AppendDev& o, int64_t slot, T ux, T uy, T uz, T w, T tau,
                                               int64_t parent) {
     if (slot >= o.capacity) return;
-    st<T>(o.ux, slot, ux);
-    st<T>(o.uy, slot, uy);
-    st<T>(o.uz, slot, uz);
-    st<T>(o.w, slot, w);
-    st<T>(o.tau, slot, tau);
-    if (o.parent) o.parent[slot] = parent;
+    stnt<T>(o.ux, slot, ux);
+    stnt<T>(o.uy, slot, uy);
+    stnt<T>(o.uz, slot, uz);
+    stnt<T>(o.w, slot, w);
+    stnt<T>(o.tau, slot, tau);
+    if (o.parent) __builtin_nontemporal_store(static_cast<long long>(parent),
+                                              reinterpret_cast<long long*>(o.parent) + slot);
 }
 
 // Surrogate sampling for the events of one wave (all 64 lanes call it
@@ -530,10 +534,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                     pa[2] = pz * iu;
                     pb[0] = pb[1] = pb[2] = T(0);
                     if (valid) {
-                        st<T>(S.p[0], j, (ux - px) * iu);
-                        st<T>(S.p[1], j, (uy - py) * iu);
-                        st<T>(S.p[2], j, (uz - pz) * iu);
-                        st<T>(S.p[9], j, t1);
+                        stnt<T>(S.p[0], j, (ux - px) * iu);
+                        stnt<T>(S.p[1], j, (uy - py) * iu);
+                        stnt<T>(S.p[2], j, (uz - pz) * iu);
+                        stnt<T>(S.p[9], j, t1);
                     }
                 }
                 if (e0 == 0) {
