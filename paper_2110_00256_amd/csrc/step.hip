@@ -520,7 +520,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                     pb[0] = esel ? ox : sx;
                     pb[1] = esel ? oy : sy;
                     pb[2] = esel ? oz : sz;
-                    if (valid) st<T>(S.p[9], j, static_cast<T>(__builtin_inf()));
+                    if (valid) stnt<T>(S.p[9], j, static_cast<T>(__builtin_inf()));
                 } else {
                     // QS photon energy gamma_gamma = (gamma - 1) xi, gamma - 1 = |u|^2/(gamma + 1)
                     const double dx = ux, dy = uy, dz = uz;
@@ -638,10 +638,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 const T um = static_cast<T>(sqrt(u2));
                 const T sc = um > T(0) ? gg / um : T(0);
                 const T px = sc * ux, py = sc * uy, pz = sc * uz;
-                st<T>(S.p[0], j, (ux - px) * iu);
-                st<T>(S.p[1], j, (uy - py) * iu);
-                st<T>(S.p[2], j, (uz - pz) * iu);
-                st<T>(S.p[9], j, t1);
+                stnt<T>(S.p[0], j, (ux - px) * iu);
+                stnt<T>(S.p[1], j, (uy - py) * iu);
+                stnt<T>(S.p[2], j, (uz - pz) * iu);
+                stnt<T>(S.p[9], j, t1);
                 const unsigned long long m = kmask[e >> 6];
                 if ((m >> (e & 63)) & 1ULL) {
                     const long long rank = kpref[e >> 6] + __popcll(m & ((1ULL << (e & 63)) - 1ULL));
