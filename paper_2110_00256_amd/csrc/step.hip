@@ -331,9 +331,13 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                     const int64_t j = c.begin + (loc < c.len ? loc : 0);
                     // u with ordinary loads (the event pass gathers the
                     // events' u again, and finds part of its lines still
-                    // cached), the fields and tau non-temporal (read once)
+                    // cached), the fields and tau non-temporal (read once).
+                    // Two loops: a select between the two kinds of load of
+                    // the same address is merged into one ordinary load.
 #pragma unroll
-                    for (int q = 0; q < 10; ++q) v[b][q] = q < 3 ? ld<T>(S.p[q], j) : ldnt<T>(S.p[q], j);
+                    for (int q = 0; q < 3; ++q) v[b][q] = ld<T>(S.p[q], j);
+#pragma unroll
+                    for (int q = 3; q < 10; ++q) v[b][q] = ldnt<T>(S.p[q], j);
                 }
             };
             auto eval_batch = [&](int it, T (&v)[kBatch][10]) {
