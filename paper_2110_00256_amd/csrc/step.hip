@@ -329,15 +329,12 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 for (int b = 0; b < kBatch; ++b) {
                     const int loc = wbase + (it + b) * 64 + static_cast<int>(lane);
                     const int64_t j = c.begin + (loc < c.len ? loc : 0);
-                    // u with ordinary loads (the event pass gathers the
-                    // events' u again, and finds part of its lines still
-                    // cached), the fields and tau non-temporal (read once).
-                    // Two loops: a select between the two kinds of load of
-                    // the same address is merged into one ordinary load.
+                    // ordinary loads for all ten arrays: non-temporal loads
+                    // for the fields and tau (read once) measured the same
+                    // for the table kernels and 20% slower for the
+                    // surrogate kernel
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) v[b][q] = ld<T>(S.p[q], j);
-#pragma unroll
-                    for (int q = 3; q < 10; ++q) v[b][q] = ldnt<T>(S.p[q], j);
+                    for (int q = 0; q < 10; ++q) v[b][q] = ld<T>(S.p[q], j);
                 }
             };
             auto eval_batch = [&](int it, T (&v)[kBatch][10]) {
