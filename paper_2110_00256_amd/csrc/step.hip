@@ -46,13 +46,9 @@ template <typename T>
 __device__ __forceinline__ void st(void* p, int64_t i, T v) {
     static_cast<T*>(p)[i] = v;
 }
-// Streaming (non-temporal) access for the particle stream: every element is
-// touched once per step, so it should not evict the lookup tables that the
-// inverse-CDF search walks from L2.
-template <typename T>
-__device__ __forceinline__ T ldnt(const void* p, int64_t i) {
-    return __builtin_nontemporal_load(static_cast<const T*>(p) + i);
-}
+// Streaming (non-temporal) stores for values written once per step and not
+// read again in it (optical depths, parent updates, products), so that they
+// do not evict the lookup tables the inverse-CDF search walks from L2.
 template <typename T>
 __device__ __forceinline__ void stnt(void* p, int64_t i, T v) {
     __builtin_nontemporal_store(v, static_cast<T*>(p) + i);
