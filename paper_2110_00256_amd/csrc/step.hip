@@ -473,9 +473,18 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             // are written from then on.
             if (tid == 0) publish(a, k, c, static_cast<unsigned long long>(total));
             long long excl = 0;   // the same in every thread once resolved
+            // The events' u and w.  Loads complete in issue order.  The table
+            // kernels gather the next round's events at the top of each round
+            // and scale them at once, which waits for the gathers there.  The
+            // surrogate kernel gathers its own round's events at the top of
+            // the round and scales them after the draws and the network, whose
+            // arithmetic then covers the gathers' latency (measured 0.95 ->
+            // 0.89 ms; the same schedule left the table kernels' time
+            // unchanged and moved FP64 results by up to 8e-13 through the
+            // compiler's operand order in |u|^2, so they keep theirs).
             int e = tid;
             T nux = T(0), nuy = T(0), nuz = T(0), nw = T(1);
-            if (e < total) {
+            if (!kSurr && e < total) {
                 const int64_t jn = c.begin + ev_loc(e);
                 nux = su * ld<T>(S.p[0], jn);
                 nuy = su * ld<T>(S.p[1], jn);
@@ -487,8 +496,18 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 const bool valid = e < total;
                 const int le = valid ? ev_loc(e) : 0;
                 const int64_t j = c.begin + le;
-                const T ux = nux, uy = nuy, uz = nuz, w = nw;
-                if (e + kBlock < total) {
+                if constexpr (kSurr) {
+                    nux = nuy = nuz = T(0);
+                    nw = T(1);
+                    if (valid) {
+                        nux = ld<T>(S.p[0], j);
+                        nuy = ld<T>(S.p[1], j);
+                        nuz = ld<T>(S.p[2], j);
+                        if (S.p[10]) nw = ld<T>(S.p[10], j);
+                    }
+                }
+                const T rux = nux, ruy = nuy, ruz = nuz, w = nw;   // scaled (table kernels) or raw
+                if (!kSurr && e + kBlock < total) {
                     const int64_t jn = c.begin + ev_loc(e + kBlock);
                     nux = su * ld<T>(S.p[0], jn);
                     nuy = su * ld<T>(S.p[1], jn);
@@ -506,6 +525,13 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 // positron; QS parent (redrawn) and photon
                 const T t1 = dev::neg_log_uniform<T>(d.u[1]);
                 const T t2 = dev::neg_log_uniform<T>(d.u[2]);
+                T ux = rux, uy = ruy, uz = ruz;
+                if constexpr (kSurr) {
+#pragma clang fp contract(off)
+                    ux = su * rux;
+                    uy = su * ruy;
+                    uz = su * ruz;
+                }
                 T pa[3], pb[3];   // BW: the electron's and positron's u; QS: the photon's u
                 if (photon) {
                     const bool esel = d.u[0] <= 0.5;   // on the 53-bit uniform, as the fold
