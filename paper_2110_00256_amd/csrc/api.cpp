@@ -285,6 +285,10 @@ extern "C" int32_t qed_context_set_units(qed_context* ctx, const qed_units* unit
             set_error("unknown unit system");
             return QED_ERR_INVALID;
     }
+    u.e_f = static_cast<float>(u.e);
+    u.b_f = static_cast<float>(u.b);
+    u.u_f = static_cast<float>(u.u);
+    u.inv_u_f = static_cast<float>(u.inv_u);
     ctx->units = u;
     return QED_OK;
 }
@@ -427,6 +431,7 @@ int32_t prepare_tables(const Units& units, const qed_step_desc* d, StepArgs& a, 
     a.po = to_append(any_photon ? d->positrons : nullptr);
     a.stats = d->stats;
     a.dt = d->dt * units.t;
+    a.dt_f = static_cast<float>(a.dt);
     a.units = units;
     a.seed = d->seed;
     a.step = d->step;

@@ -265,10 +265,18 @@ __device__ __forceinline__ float dlog(float x) { return logf(x); }
 __device__ __forceinline__ double dexp(double x) { return exp(x); }
 __device__ __forceinline__ float dexp(float x) { return expf(x); }
 
+// A uniform parameter in the compute precision: the FP64 value, or its copy
+// rounded to FP32 on the host (the same value a conversion here would give).
+template <typename T>
+__device__ __forceinline__ T par(double d, float f) {
+    if constexpr (sizeof(T) == 8) return d;
+    else return f;
+}
+
 // Interval index n in [0, N-2] and weight f = t - n for ln chi on the grid.
 template <typename T>
 __device__ __forceinline__ void grid_pos(const TableDev& t, T lnchi, int& n, T& f) {
-    const T x = (lnchi - static_cast<T>(t.ln_chi_min)) * static_cast<T>(t.inv_dlnchi);
+    const T x = (lnchi - par<T>(t.ln_chi_min, t.ln_chi_min_f)) * par<T>(t.inv_dlnchi, t.inv_dlnchi_f);
     int k = static_cast<int>(floor(x));
     k = k < 0 ? 0 : (k > t.n_chi - 2 ? t.n_chi - 2 : k);
     n = k;
@@ -317,10 +325,10 @@ template <typename T, typename S>
 __device__ __forceinline__ T rate_bw(const S* ln_t, const TableDev& t, T chi, T gamma_g) {
     if (!(chi > T(0)) || !(gamma_g > T(0))) return T(0);
     T y;
-    if (chi < static_cast<T>(t.chi_min)) {
-        y = tload<T>(ln_t, 0) - T(8.0 / 3.0) * (T(1) / chi - static_cast<T>(1.0 / t.chi_min));
-    } else if (chi > static_cast<T>(t.chi_max)) {
-        y = tload<T>(ln_t, t.n_chi - 1) - T(1.0 / 3.0) * (dlog(chi) - static_cast<T>(log(t.chi_max)));
+    if (chi < par<T>(t.chi_min, t.chi_min_f)) {
+        y = tload<T>(ln_t, 0) - T(8.0 / 3.0) * (T(1) / chi - par<T>(t.inv_chi_min, t.inv_chi_min_f));
+    } else if (chi > par<T>(t.chi_max, t.chi_max_f)) {
+        y = tload<T>(ln_t, t.n_chi - 1) - T(1.0 / 3.0) * (dlog(chi) - par<T>(t.ln_chi_max, t.ln_chi_max_f));
     } else {
         int n;
         T f;
@@ -336,9 +344,9 @@ __device__ __forceinline__ T rate_bw(const S* ln_t, const TableDev& t, T chi, T 
 template <typename T, typename S>
 __device__ __forceinline__ T rate_qs(const S* ln_g, const TableDev& t, T chi, T gamma) {
     T y;
-    if (!(chi >= static_cast<T>(t.chi_min))) {
+    if (!(chi >= par<T>(t.chi_min, t.chi_min_f))) {
         y = tload<T>(ln_g, 0);
-    } else if (chi > static_cast<T>(t.chi_max)) {
+    } else if (chi > par<T>(t.chi_max, t.chi_max_f)) {
         y = tload<T>(ln_g, t.n_chi - 1);
     } else {
         int n;
@@ -354,8 +362,8 @@ __device__ __forceinline__ T rate_qs(const S* ln_g, const TableDev& t, T chi, T 
 template <typename T>
 __device__ __forceinline__ void row_pos(const TableDev& t, T chi, int& n, T& f) {
     T c = chi;
-    if (!(c >= static_cast<T>(t.chi_min))) c = static_cast<T>(t.chi_min);
-    if (c > static_cast<T>(t.chi_max)) c = static_cast<T>(t.chi_max);
+    if (!(c >= par<T>(t.chi_min, t.chi_min_f))) c = par<T>(t.chi_min, t.chi_min_f);
+    if (c > par<T>(t.chi_max, t.chi_max_f)) c = par<T>(t.chi_max, t.chi_max_f);
     grid_pos<T>(t, dlog(c), n, f);
 }
 
@@ -450,7 +458,7 @@ __device__ __forceinline__ T sample_qs_lnxi_lr(const TableDev& t, T chi, T lr) {
     row_pos<T>(t, chi, n, f);
     const int nf = t.n_frac;
     const S* pp = cdf_ptr<S>(t) + 2 * static_cast<size_t>(n) * nf;
-    const T lmin = static_cast<T>(t.ln_frac_min);
+    const T lmin = par<T>(t.ln_frac_min, t.ln_frac_min_f);
     const T l0 = pair_value<T, S>(pp, f, 0);
     if (lr < l0) return lmin + T(3) * (lr - l0);
     const int lo = upper_bound_row<T, S>(pp, f, lr, nf);

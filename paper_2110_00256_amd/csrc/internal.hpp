@@ -37,6 +37,12 @@ struct TableDev {
     double chi_min, chi_max;
     double ln_chi_min, inv_dlnchi;   // t = (ln chi - ln chi_min) * inv_dlnchi
     double frac_min, ln_frac_min;
+    double inv_chi_min, ln_chi_max;
+    // The same parameters rounded to FP32 on the host: FP32 kernels read
+    // them as uniform kernel arguments (scalar registers) instead of
+    // converting the FP64 ones into vector registers that live across the
+    // particle loops.
+    float chi_min_f, chi_max_f, ln_chi_min_f, inv_dlnchi_f, ln_frac_min_f, inv_chi_min_f, ln_chi_max_f;
 };
 
 struct SetDev {
@@ -70,6 +76,7 @@ struct ChunkDesc {
 // energies in m_e c^2).  All 1 for SI.
 struct Units {
     double e = 1.0, b = 1.0, u = 1.0, inv_u = 1.0;   // multiply a caller value by these
+    float e_f = 1.0f, b_f = 1.0f, u_f = 1.0f, inv_u_f = 1.0f;   // the same, rounded to FP32
     double t = 1.0;        // seconds per caller time unit
     double energy = 1.0;   // m_e c^2 per caller energy unit
     double length = 1.0;   // metres per caller length unit
@@ -91,6 +98,7 @@ struct StepArgs {
     SurrogateDev bw_surr, qs_surr;  // valid when use_*_surr
     int32_t use_bw_surr, use_qs_surr;
     double dt;
+    float dt_f;                     // dt rounded to FP32
     unsigned long long seed, step;
     double photon_min_energy;
     int32_t chi_mode;

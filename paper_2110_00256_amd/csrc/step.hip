@@ -278,7 +278,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
         }
 
         // ---------------- phase 1: stream, evolve, flag
-        const T dt = static_cast<T>(a.dt);
+        const T dt = dev::par<T>(a.dt, a.dt_f);
         // each wave streams its own contiguous quarter of the chunk and
         // appends its events (chunk positions, in order) to its region of
         // evlist with a running count: no block-wide list pass is needed
@@ -293,8 +293,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                     const int64_t j = c.begin + loc;
                     ev = S.flags[j] != 0;
                     if (ev) {
-                        const T su = static_cast<T>(a.units.u), se = static_cast<T>(a.units.e),
-                                sb = static_cast<T>(a.units.b);
+                        const T su = dev::par<T>(a.units.u, a.units.u_f), se = dev::par<T>(a.units.e, a.units.e_f),
+                                sb = dev::par<T>(a.units.b, a.units.b_f);
                         const T ux = su * ld<T>(S.p[0], j), uy = su * ld<T>(S.p[1], j), uz = su * ld<T>(S.p[2], j);
                         const T ex = se * ld<T>(S.p[3], j), ey = se * ld<T>(S.p[4], j), ez = se * ld<T>(S.p[5], j);
                         const T bx = sb * ld<T>(S.p[6], j), by = sb * ld<T>(S.p[7], j), bz = sb * ld<T>(S.p[8], j);
@@ -339,7 +339,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                     // caller units -> u = p/(m_e c), V/m, T (factors 1 for SI)
 #pragma unroll
                     for (int q = 0; q < 9; ++q)
-                        v[b][q] *= static_cast<T>(q < 3 ? a.units.u : q < 6 ? a.units.e : a.units.b);
+                        v[b][q] *= q < 3 ? dev::par<T>(a.units.u, a.units.u_f)
+                                         : q < 6 ? dev::par<T>(a.units.e, a.units.e_f) : dev::par<T>(a.units.b, a.units.b_f);
                     const int loc = wbase + (it + b) * 64 + static_cast<int>(lane);
                     bool ev = false;
                     if (loc < c.len) {
@@ -453,7 +454,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
         // slot = exclusive prefix of the stream's product counts over earlier
         // chunks (decoupled look-back) + the event's rank in this chunk.
         const bool thresh = !photon && a.photon_min_energy > 0.0;
-        const T su = static_cast<T>(a.units.u), iu = static_cast<T>(a.units.inv_u);
+        const T su = dev::par<T>(a.units.u, a.units.u_f), iu = dev::par<T>(a.units.inv_u, a.units.inv_u_f);
         // sample of event e from its chi (or surrogate sample) `cs` and u0
         auto sample_of = [&](bool have, T cs, double u0) -> T {
             if (photon) {

@@ -91,6 +91,15 @@ qedmi::TableDev qed_table::view() const {
     v.inv_dlnchi = (p.n_chi - 1) / (std::log(p.chi_max) - std::log(p.chi_min));
     v.frac_min = p.frac_min;
     v.ln_frac_min = p.process == QED_PROC_QS ? std::log(p.frac_min) : 0.0;
+    v.inv_chi_min = 1.0 / p.chi_min;
+    v.ln_chi_max = std::log(p.chi_max);
+    v.chi_min_f = static_cast<float>(v.chi_min);
+    v.chi_max_f = static_cast<float>(v.chi_max);
+    v.ln_chi_min_f = static_cast<float>(v.ln_chi_min);
+    v.inv_dlnchi_f = static_cast<float>(v.inv_dlnchi);
+    v.ln_frac_min_f = static_cast<float>(v.ln_frac_min);
+    v.inv_chi_min_f = static_cast<float>(v.inv_chi_min);
+    v.ln_chi_max_f = static_cast<float>(v.ln_chi_max);
     return v;
 }
 
