@@ -513,18 +513,19 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             // are written from then on.
             if (tid == 0) publish(a, k, c, static_cast<unsigned long long>(total));
             long long excl = 0;   // the same in every thread once resolved
-            // The events' u and w.  Loads complete in issue order.  The table
-            // kernels gather the next round's events at the top of each round
-            // and scale them at once, which waits for the gathers there.  The
-            // surrogate kernel gathers its own round's events at the top of
-            // the round and scales them after the draws and the network, whose
-            // arithmetic then covers the gathers' latency (measured 0.95 ->
-            // 0.89 ms; the same schedule left the table kernels' time
-            // unchanged and moved FP64 results by up to 8e-13 through the
-            // compiler's operand order in |u|^2, so they keep theirs).
+            // The events' u and w.  Loads complete in issue order.  The FP32
+            // kernels gather each round's own events at the top of the round
+            // and scale them after the draws (and the network), whose
+            // arithmetic then covers the gathers' latency: surrogate step
+            // 0.95 -> 0.89 ms, FP32 production calls 4% faster.  The FP64
+            // kernel gathers the next round's events at the top of each round
+            // and scales them at once, which waits for the gathers there; the
+            // other schedule measured the same for it and moved its results by
+            // up to 8e-13 through the compiler's operand order in |u|^2.
+            constexpr bool kGatherOwn = kSurr || sizeof(T) == 4;
             int e = tid;
             T nux = T(0), nuy = T(0), nuz = T(0), nw = T(1);
-            if (!kSurr && e < total) {
+            if (!kGatherOwn && e < total) {
                 const int64_t jn = c.begin + ev_loc(e);
                 nux = su * ld<T>(S.p[0], jn);
                 nuy = su * ld<T>(S.p[1], jn);
@@ -536,7 +537,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 const bool valid = e < total;
                 const int le = valid ? ev_loc(e) : 0;
                 const int64_t j = c.begin + le;
-                if constexpr (kSurr) {
+                if constexpr (kGatherOwn) {
                     nux = nuy = nuz = T(0);
                     nw = T(1);
                     if (valid) {
@@ -547,7 +548,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                     }
                 }
                 const T rux = nux, ruy = nuy, ruz = nuz, w = nw;   // scaled (table kernels) or raw
-                if (!kSurr && e + kBlock < total) {
+                if (!kGatherOwn && e + kBlock < total) {
                     const int64_t jn = c.begin + ev_loc(e + kBlock);
                     nux = su * ld<T>(S.p[0], jn);
                     nuy = su * ld<T>(S.p[1], jn);
@@ -566,7 +567,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 const T t1 = dev::neg_log_uniform<T>(d.u[1]);
                 const T t2 = dev::neg_log_uniform<T>(d.u[2]);
                 T ux = rux, uy = ruy, uz = ruz;
-                if constexpr (kSurr) {
+                if constexpr (kGatherOwn) {
 #pragma clang fp contract(off)
                     ux = su * rux;
                     uy = su * ruy;
