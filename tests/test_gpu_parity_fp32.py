@@ -16,7 +16,7 @@ torch = pytest.importorskip("torch")
 import paper_2110_00256_amd as Q  # noqa: E402
 import qed_inputs as QI  # noqa: E402
 from oracle import oracle as O  # noqa: E402
-from tests.gpu_util import host, lib_tables, oracle_tables, rel_close  # noqa: E402
+from tests.gpu_util import compare_append, host, lib_tables, oracle_tables, rel_close  # noqa: E402
 
 RTOL = 1e-5
 TIE = 1e-6
@@ -162,3 +162,44 @@ def test_comp32_beats_fp32_on_copropagating(ctx):
     assert err[Q.CHI_COMP32] < 1e-4
     assert err[Q.CHI_FP64] < 1e-4
     assert err[Q.CHI_FP32] > 10 * err[Q.CHI_COMP32]
+
+
+@pytest.mark.parametrize("every", [1, 3, 97])
+def test_fp32_standalone_generate(ctx, tabs, every):
+    """The FP32 production calls (pair generation; photon emission with the
+    parent's momentum update, Sec. 3.1, 3.2) against the oracle on the same
+    FP32 inputs, over a count that leaves a partial last chunk: flags on
+    every particle, on one in three and on one in 97 (most slices of 64
+    then hold no or one flagged particle).  Counts and parent ids exact;
+    momenta within 1e-5 of the parent's |u|, optical depths and weights
+    within 1e-5 relative."""
+    (bw, qs), (obw, oqs) = tabs
+    n = 9037
+    for photon in (False, True):
+        pop = QI.plane_wave_counter(n, 11, photon, stream=int(photon))
+        pop = {k: np.asarray(v, dtype=np.float32).astype(np.float64) for k, v in pop.items()}
+        sp = O.PHOTON if photon else O.ELECTRON
+        flags = (np.arange(n) % every == 0).astype(np.uint8)
+        d = {k: torch.as_tensor(v).to("cuda", torch.float32) for k, v in pop.items()}
+        d["tau"] = torch.ones(n, dtype=torch.float32, device="cuda")
+        p = Q.particles(d, sp, 777)
+        op = O.Particles(pop, sp, id_base=777, tau=np.ones(n))
+        fl = torch.as_tensor(flags).cuda()
+        a1, a2 = Q.AppendBuffer(n, torch.float32), Q.AppendBuffer(n, torch.float32)
+        o1, o2 = O.Append(n), O.Append(n)
+        if photon:
+            Q.generate_pairs(ctx, bw, p, fl, 10, 42, a1, a2)
+            O.generate(obw, oqs, op, flags, 10, 42, o1, o2)
+        else:
+            Q.generate_photon_and_update_momentum(ctx, qs, p, fl, 10, 42, a1)
+            O.generate(obw, oqs, op, flags, 10, 42, o1)
+        torch.cuda.synchronize()
+        assert o1.count == int(flags.sum())
+        umag = np.sqrt(pop["ux"] ** 2 + pop["uy"] ** 2 + pop["uz"] ** 2)
+        pu = umag[o1["parent"][: o1.count] - 777]
+        compare_append(a1, o1, RTOL, "generate a1", parent_umag=pu)
+        if photon:
+            compare_append(a2, o2, RTOL, "generate a2", parent_umag=pu)
+        assert rel_close(host(d["tau"]), op["tau"], RTOL) <= 1.0
+        for k in ("ux", "uy", "uz"):
+            assert rel_close(host(d[k]), op[k], RTOL, floor=np.maximum(umag, 1e-30)) <= 1.0
