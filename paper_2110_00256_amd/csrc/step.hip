@@ -513,47 +513,25 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             // are written from then on.
             if (tid == 0) publish(a, k, c, static_cast<unsigned long long>(total));
             long long excl = 0;   // the same in every thread once resolved
-            // The events' u and w.  Loads complete in issue order.  The FP32
-            // kernels gather each round's own events at the top of the round
-            // and scale them after the draws (and the network), whose
-            // arithmetic then covers the gathers' latency: surrogate step
-            // 0.95 -> 0.89 ms, FP32 production calls 4% faster.  The FP64
-            // kernel gathers the next round's events at the top of each round
-            // and scales them at once, which waits for the gathers there; the
-            // other schedule measured the same for it and moved its results by
-            // up to 8e-13 through the compiler's operand order in |u|^2.
-            constexpr bool kGatherOwn = kSurr || sizeof(T) == 4;
-            int e = tid;
-            T nux = T(0), nuy = T(0), nuz = T(0), nw = T(1);
-            if (!kGatherOwn && e < total) {
-                const int64_t jn = c.begin + ev_loc(e);
-                nux = su * ld<T>(S.p[0], jn);
-                nuy = su * ld<T>(S.p[1], jn);
-                nuz = su * ld<T>(S.p[2], jn);
-                if (S.p[10]) nw = ld<T>(S.p[10], jn);
-            }
+            // Each round's events' u and w are gathered at the top of the
+            // round and scaled only after the draws (and the network), whose
+            // arithmetic then covers the gathers' latency.  Loads complete in
+            // issue order, so a value scaled as soon as it is gathered waits
+            // for the gather where it is issued: gathering the next round's
+            // events at the top of each round and scaling them there measured
+            // 0.95 against 0.89 ms on the surrogate step and 3-4% slower
+            // production calls.
 #pragma unroll 1
-            for (int e0 = 0; e0 < total; e0 += kBlock, e += kBlock) {
+            for (int e0 = 0, e = tid; e0 < total; e0 += kBlock, e += kBlock) {
                 const bool valid = e < total;
                 const int le = valid ? ev_loc(e) : 0;
                 const int64_t j = c.begin + le;
-                if constexpr (kGatherOwn) {
-                    nux = nuy = nuz = T(0);
-                    nw = T(1);
-                    if (valid) {
-                        nux = ld<T>(S.p[0], j);
-                        nuy = ld<T>(S.p[1], j);
-                        nuz = ld<T>(S.p[2], j);
-                        if (S.p[10]) nw = ld<T>(S.p[10], j);
-                    }
-                }
-                const T rux = nux, ruy = nuy, ruz = nuz, w = nw;   // scaled (table kernels) or raw
-                if (!kGatherOwn && e + kBlock < total) {
-                    const int64_t jn = c.begin + ev_loc(e + kBlock);
-                    nux = su * ld<T>(S.p[0], jn);
-                    nuy = su * ld<T>(S.p[1], jn);
-                    nuz = su * ld<T>(S.p[2], jn);
-                    if (S.p[10]) nw = ld<T>(S.p[10], jn);
+                T rux = T(0), ruy = T(0), ruz = T(0), w = T(1);
+                if (valid) {
+                    rux = ld<T>(S.p[0], j);
+                    ruy = ld<T>(S.p[1], j);
+                    ruz = ld<T>(S.p[2], j);
+                    if (S.p[10]) w = ld<T>(S.p[10], j);
                 }
                 const int64_t parent = S.id_base + j;
                 const dev::Draws d = dev::draws<sizeof(T) == 4>(a.seed, static_cast<unsigned long long>(parent), a.step,
@@ -566,8 +544,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 // positron; QS parent (redrawn) and photon
                 const T t1 = dev::neg_log_uniform<T>(d.u[1]);
                 const T t2 = dev::neg_log_uniform<T>(d.u[2]);
-                T ux = rux, uy = ruy, uz = ruz;
-                if constexpr (kGatherOwn) {
+                T ux, uy, uz;
+                {
 #pragma clang fp contract(off)
                     ux = su * rux;
                     uy = su * ruy;
@@ -588,7 +566,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 } else {
                     // QS photon energy gamma_gamma = (gamma - 1) xi, gamma - 1 = |u|^2/(gamma + 1)
                     const double dx = ux, dy = uy, dz = uz;
-                    const double u2 = dx * dx + dy * dy + dz * dz;
+                    // FP64: the terms of |u|^2 in a fixed order, so that the
+                    // results do not depend on how the compiler orders them
+                    const double u2 = sizeof(T) == 8 ? fma(dz, dz, fma(dx, dx, dy * dy)) : dx * dx + dy * dy + dz * dz;
                     const T gg = static_cast<T>(u2 / (sqrt(1.0 + u2) + 1.0)) * xi;
                     const T um = static_cast<T>(sqrt(u2));
                     const T sc = um > T(0) ? gg / um : T(0);
