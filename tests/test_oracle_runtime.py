@@ -133,6 +133,39 @@ def test_step_kinematics_conservation_and_order(tables64):
             assert np.all(ge + gp - gg <= bound * (1 + 1e-9) + 1e-12)
 
 
+def test_generate_equals_step_on_its_own_events(tables64):
+    """The production calls (pair generation, photon emission with momentum
+    update; Fig. 1, Sec. 3.1, 3.2) are the event half of the step: given
+    the step's own event flags, they create the same products in the same
+    order, give the flagged parents the same momenta and optical depths,
+    and leave every other particle as it was.  The two oracle routines are
+    separate code paths, so this pins each against the other."""
+    bw, qs = tables64
+    el, ph = QI.parity_population(seed=4, n=3000)
+    for pop, sp in ((el, O.ELECTRON), (ph, O.PHOTON)):
+        ps = O.Particles(pop, sp, id_base=500)
+        O.init_optical_depth(ps, seed=4)
+        tau0 = ps["tau"].copy()
+        pg = O.Particles(pop, sp, id_base=500, tau=tau0)
+        s1, s2 = O.Append(3000), O.Append(3000)
+        flags = np.zeros(ps.n, dtype=np.uint8)
+        O.step(bw, qs, ps, 1e-16, seed=4, step_idx=7, a1=s1, a2=s2, flags=flags)
+        assert 0 < int(flags.sum()) < ps.n
+        g1, g2 = O.Append(3000), O.Append(3000)
+        O.generate(bw, qs, pg, flags, 4, 7, g1, g2 if sp == O.PHOTON else None)
+        assert g1.count == s1.count == int(flags.sum())
+        for k in ("parent", "ux", "uy", "uz", "w", "tau"):
+            np.testing.assert_array_equal(g1[k], s1[k])
+            if sp == O.PHOTON:
+                np.testing.assert_array_equal(g2[k], s2[k])
+        ev = flags == 1
+        for k in ("ux", "uy", "uz", "tau"):
+            np.testing.assert_array_equal(pg[k][ev], ps[k][ev])
+        np.testing.assert_array_equal(pg["tau"][~ev], tau0[~ev])
+        for k in ("ux", "uy", "uz"):
+            np.testing.assert_array_equal(pg[k][~ev], np.asarray(pop[k], dtype=np.float64)[~ev])
+
+
 def test_init_optical_depth_keying():
     pop = _fixed_population(64, 10.0, 1e12, False)
     p = O.Particles(pop, O.POSITRON, id_base=2**40)
