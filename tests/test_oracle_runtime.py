@@ -135,7 +135,8 @@ def test_step_kinematics_conservation_and_order(tables64):
 
 def test_generate_equals_step_on_its_own_events(tables64):
     """The production calls (pair generation, photon emission with momentum
-    update; Fig. 1, Sec. 3.1, 3.2) are the event half of the step: given
+    update; Fig. 1, Sec. 3.1, 3.2) are the event half of the step, and the
+    optical-depth evolution call its other half: given
     the step's own event flags, they create the same products in the same
     order, give the flagged parents the same momenta and optical depths,
     and leave every other particle as it was.  The two oracle routines are
@@ -164,6 +165,13 @@ def test_generate_equals_step_on_its_own_events(tables64):
         np.testing.assert_array_equal(pg["tau"][~ev], tau0[~ev])
         for k in ("ux", "uy", "uz"):
             np.testing.assert_array_equal(pg[k][~ev], np.asarray(pop[k], dtype=np.float64)[~ev])
+        # and the evolution call is its other half: the same flags, and the
+        # step's optical depths wherever there was no event
+        pe = O.Particles(pop, sp, id_base=500, tau=tau0)
+        fe = np.zeros(pe.n, dtype=np.uint8)
+        O.evolve(bw if sp == O.PHOTON else qs, pe, 1e-16, fe)
+        np.testing.assert_array_equal(fe, flags)
+        np.testing.assert_array_equal(pe["tau"][~ev], ps["tau"][~ev])
 
 
 def test_init_optical_depth_keying():
