@@ -134,13 +134,14 @@ def test_step_kinematics_conservation_and_order(tables64):
 
 
 def test_generate_equals_step_on_its_own_events(tables64):
-    """The production calls (pair generation, photon emission with momentum
-    update; Fig. 1, Sec. 3.1, 3.2) are the event half of the step, and the
-    optical-depth evolution call its other half: given
-    the step's own event flags, they create the same products in the same
-    order, give the flagged parents the same momenta and optical depths,
-    and leave every other particle as it was.  The two oracle routines are
-    separate code paths, so this pins each against the other."""
+    """The step of Fig. 1 split into the paper's separate calls: the
+    optical-depth evolution gives the step's event flags and, where there is
+    no event, its optical depths; the production calls (pair generation,
+    photon emission with momentum update; Sec. 3.1, 3.2) on those flags
+    create the same products in the same order, give the flagged parents
+    the same momenta and optical depths and leave every other particle as
+    it was.  The oracle's step and its separate calls are different code
+    paths, so this pins each against the other."""
     bw, qs = tables64
     el, ph = QI.parity_population(seed=4, n=3000)
     for pop, sp in ((el, O.ELECTRON), (ph, O.PHOTON)):
