@@ -133,15 +133,17 @@ def test_step_kinematics_conservation_and_order(tables64):
             assert np.all(ge + gp - gg <= bound * (1 + 1e-9) + 1e-12)
 
 
-def test_generate_equals_step_on_its_own_events(tables64):
+@pytest.mark.parametrize("emin", [0.0, 30.0])
+def test_generate_equals_step_on_its_own_events(tables64, emin):
     """The step of Fig. 1 split into the paper's separate calls: the
     optical-depth evolution gives the step's event flags and, where there is
     no event, its optical depths; the production calls (pair generation,
     photon emission with momentum update; Sec. 3.1, 3.2) on those flags
     create the same products in the same order, give the flagged parents
     the same momenta and optical depths and leave every other particle as
-    it was.  The oracle's step and its separate calls are different code
-    paths, so this pins each against the other."""
+    it was, with and without a photon energy threshold.  The oracle's step
+    and its separate calls are different code paths, so this pins each
+    against the other."""
     bw, qs = tables64
     el, ph = QI.parity_population(seed=4, n=3000)
     for pop, sp in ((el, O.ELECTRON), (ph, O.PHOTON)):
@@ -151,11 +153,15 @@ def test_generate_equals_step_on_its_own_events(tables64):
         pg = O.Particles(pop, sp, id_base=500, tau=tau0)
         s1, s2 = O.Append(3000), O.Append(3000)
         flags = np.zeros(ps.n, dtype=np.uint8)
-        O.step(bw, qs, ps, 1e-16, seed=4, step_idx=7, a1=s1, a2=s2, flags=flags)
+        O.step(bw, qs, ps, 1e-16, seed=4, step_idx=7, a1=s1, a2=s2, photon_min_energy=emin, flags=flags)
         assert 0 < int(flags.sum()) < ps.n
         g1, g2 = O.Append(3000), O.Append(3000)
-        O.generate(bw, qs, pg, flags, 4, 7, g1, g2 if sp == O.PHOTON else None)
-        assert g1.count == s1.count == int(flags.sum())
+        O.generate(bw, qs, pg, flags, 4, 7, g1, g2 if sp == O.PHOTON else None, photon_min_energy=emin)
+        assert g1.count == s1.count
+        if sp == O.PHOTON or emin == 0.0:
+            assert g1.count == int(flags.sum())
+        else:   # the photon threshold keeps some photons and drops others
+            assert 0 < g1.count < int(flags.sum())
         for k in ("parent", "ux", "uy", "uz", "w", "tau"):
             np.testing.assert_array_equal(g1[k], s1[k])
             if sp == O.PHOTON:
