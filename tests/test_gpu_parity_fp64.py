@@ -397,6 +397,33 @@ def test_standalone_generate_matches_oracle(ctx, tabs, every):
             assert rel_close(host(d[k]), op[k], RTOL, floor=1.0) <= 1.0
 
 
+@pytest.mark.parametrize("every", [1, 3])
+def test_standalone_photon_emission_with_threshold(ctx, tabs, every):
+    """Photon emission with a photon energy threshold (Sec. 3.2): every
+    flagged lepton recoils and redraws its optical depth, only photons at or
+    above the threshold are appended, in parent order, counts and parents
+    exact against the oracle."""
+    (bw, qs), (obw, oqs) = tabs
+    n = 9000
+    pop = QI.plane_wave_counter(n, 12, False, stream=0)
+    flags = (np.arange(n) % every == 0).astype(np.uint8)
+    op = O.Particles(pop, O.ELECTRON, id_base=91)
+    O.init_optical_depth(op, 12)
+    d = dev_pop(pop, torch.float64, tau=op["tau"])
+    p = Q.particles(d, O.ELECTRON, 91)
+    fl = torch.as_tensor(flags).cuda()
+    a1, o1 = Q.AppendBuffer(n, torch.float64), O.Append(n)
+    emin = 30.0
+    Q.generate_photon_and_update_momentum(ctx, qs, p, fl, 12, 5, a1, photon_min_energy=emin)
+    O.generate(obw, oqs, op, flags, 12, 5, o1, photon_min_energy=emin)
+    torch.cuda.synchronize()
+    assert 0 < o1.count < int(flags.sum())
+    compare_append(a1, o1, RTOL, "thresholded photons")
+    assert rel_close(host(d["tau"]), op["tau"], RTOL) <= 1.0
+    for k in ("ux", "uy", "uz"):
+        assert rel_close(host(d[k]), op[k], RTOL, floor=1.0) <= 1.0
+
+
 def test_table_rate_and_sample_match_oracle(ctx, tabs):
     """The runtime rate and inverse-CDF sampling functions in isolation, over
     chi inside and outside the table range and u over (0, 1)."""
